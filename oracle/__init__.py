@@ -1,0 +1,224 @@
+"""CPU oracle for the negacyclic NTT (TEST INFRASTRUCTURE ONLY).
+
+Only the test suite, the smoke check and the benchmark's ``cpu_baseline`` leg
+may import this package.  The product library never imports, links or calls
+it, and it imports nothing from the product library.
+
+The arithmetic lives in ``ntt_oracle.c`` (plain radix-2 loops and the plain
+definitions, unsigned __int128 products and ``%``); this module only compiles
+it with gcc on first use and marshals numpy arrays.  ``py_ref`` holds a second,
+pure-Python big-integer version of the definitions for tiny sizes.
+
+Paper: Chameleon (arXiv 2410.05934), Sec. II-D and Eq. (1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ntt_oracle.c")
+_LIB = os.path.join(_HERE, "libntt_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force: bool = False) -> str:
+    """Compile ntt_oracle.c into libntt_oracle.so with gcc (plain -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+            sig = {
+                "orc_powmod": (u64, [u64, u64, u64]),
+                "orc_is_prime": (i32, [u64]),
+                "orc_smallest_qnr": (u64, [u64]),
+                "orc_psi": (u64, [u32, u64]),
+                "orc_invmod": (u64, [u64, u64]),
+                "orc_bitrev": (u32, [u32, i32]),
+                "orc_forward": (i32, [_u64p, u32, u64]),
+                "orc_inverse": (i32, [_u64p, u32, u64]),
+                "orc_forward_at": (u64, [_u64p, u32, u64, u32]),
+                "orc_inverse_at": (u64, [_u64p, u32, u64, u32]),
+                "orc_negacyclic_at": (u64, [_u64p, _u64p, u32, u64, u32]),
+                "orc_schoolbook": (None, [_u64p, _u64p, _u64p, u32, u64]),
+                "orc_pointwise_mul": (None, [_u64p, _u64p, _u64p, u64, u64]),
+                "orc_mac": (None, [_u64p, ctypes.POINTER(_u64p), ctypes.POINTER(_u64p), u32, u64, u64]),
+                "orc_polymul": (i32, [_u64p, _u64p, _u64p, u32, u64]),
+                "orc_forward_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
+                "orc_inverse_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
+                "orc_num_cores": (i32, []),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(lib, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.uint64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_u64p)
+
+
+def _u64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a).astype(np.uint64, copy=False))
+
+
+# -- number theory -----------------------------------------------------------
+
+def is_prime(n: int) -> bool:
+    return bool(_load().orc_is_prime(int(n)))
+
+
+def powmod(a: int, e: int, q: int) -> int:
+    return int(_load().orc_powmod(int(a), int(e), int(q)))
+
+
+def smallest_qnr(q: int) -> int:
+    return int(_load().orc_smallest_qnr(int(q)))
+
+
+def psi(N: int, q: int) -> int:
+    """The oracle's primitive 2N-th root (0 if q is not admissible)."""
+    return int(_load().orc_psi(int(N), int(q)))
+
+
+def bitrev(x: int, bits: int) -> int:
+    return int(_load().orc_bitrev(int(x), int(bits)))
+
+
+def num_cores() -> int:
+    return int(_load().orc_num_cores())
+
+
+# -- transforms --------------------------------------------------------------
+
+def _check_rows(a: np.ndarray, moduli) -> tuple[np.ndarray, np.ndarray, int, int, int]:
+    a = _u64(a).copy()
+    mod = _u64(np.atleast_1d(moduli))
+    N = a.shape[-1]
+    L = mod.shape[0]
+    if a.ndim == 1:
+        a = a.reshape(1, 1, N)
+    if a.shape[-2] != L and not (a.ndim == 2 and L == 1):
+        raise ValueError("limb axis does not match the number of moduli")
+    batch = a.size // (L * N)
+    return a, mod, batch, L, N
+
+
+def forward(a, moduli, nthreads: int = 0) -> np.ndarray:
+    """Forward negacyclic NTT (CT, natural in, bit-reversed out) of
+    data[..., L, N] with moduli[L]; returns a new uint64 array."""
+    shape = np.shape(a)
+    x, mod, batch, L, N = _check_rows(a, moduli)
+    rc = _load().orc_forward_batch(_p(x), batch, L, N, _p(mod), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle forward: inadmissible (N, q)")
+    return x.reshape(shape)
+
+
+def inverse(a, moduli, nthreads: int = 0) -> np.ndarray:
+    """Inverse negacyclic NTT (GS, bit-reversed in, natural out, times N^-1)."""
+    shape = np.shape(a)
+    x, mod, batch, L, N = _check_rows(a, moduli)
+    rc = _load().orc_inverse_batch(_p(x), batch, L, N, _p(mod), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle inverse: inadmissible (N, q)")
+    return x.reshape(shape)
+
+
+def forward_at(a, q: int, j: int) -> int:
+    """One output of the forward transform from its definition, O(N)."""
+    x = _u64(a)
+    return int(_load().orc_forward_at(_p(x), x.shape[-1], int(q), int(j)))
+
+
+def inverse_at(ahat, q: int, i: int) -> int:
+    x = _u64(ahat)
+    return int(_load().orc_inverse_at(_p(x), x.shape[-1], int(q), int(i)))
+
+
+def negacyclic_at(a, b, q: int, k: int) -> int:
+    """One coefficient of a*b mod (x^N+1, q) from its definition, O(N)."""
+    x, y = _u64(a), _u64(b)
+    return int(_load().orc_negacyclic_at(_p(x), _p(y), x.shape[-1], int(q), int(k)))
+
+
+def schoolbook(a, b, q: int) -> np.ndarray:
+    x, y = _u64(a), _u64(b)
+    c = np.empty_like(x)
+    _load().orc_schoolbook(_p(c), _p(x), _p(y), x.shape[-1], int(q))
+    return c
+
+
+def pointwise_mul(a, b, moduli) -> np.ndarray:
+    """c = a (.) b mod q_l for data[..., L, N]."""
+    x, y = _u64(a), _u64(b)
+    mod = _u64(np.atleast_1d(moduli))
+    N, L = x.shape[-1], mod.shape[0]
+    xr = x.reshape(-1, L, N)
+    yr = y.reshape(-1, L, N)
+    c = np.empty_like(xr)
+    lib = _load()
+    for p in range(xr.shape[0]):
+        for l in range(L):
+            xa = np.ascontiguousarray(xr[p, l])
+            ya = np.ascontiguousarray(yr[p, l])
+            ca = np.empty(N, dtype=np.uint64)
+            lib.orc_pointwise_mul(_p(ca), _p(xa), _p(ya), N, int(mod[l]))
+            c[p, l] = ca
+    return c.reshape(x.shape)
+
+
+def mac(a, key, moduli, rows: int, cols: int) -> np.ndarray:
+    """Grouped multiply-accumulate.
+
+    a[P][L][N] are P transformed operands; operand p belongs to group
+    g = p // rows at row r = p % rows; key[rows][cols][L][N].
+    out[g][c] = sum over the rows r present in group g of a[g*rows + r] (.) key[r][c].
+    The last group may be partial (fewer than `rows` operands).
+    """
+    x, k = _u64(a), _u64(key)
+    mod = _u64(np.atleast_1d(moduli))
+    P, L, N = x.shape
+    G = (P + rows - 1) // rows
+    out = np.empty((G, cols, L, N), dtype=np.uint64)
+    lib = _load()
+    for g in range(G):
+        present = [r for r in range(rows) if g * rows + r < P]
+        for c in range(cols):
+            for l in range(L):
+                xs = [np.ascontiguousarray(x[g * rows + r, l]) for r in present]
+                ks = [np.ascontiguousarray(k[r, c, l]) for r in present]
+                xp = (_u64p * len(xs))(*[_p(v) for v in xs])
+                kp = (_u64p * len(ks))(*[_p(v) for v in ks])
+                o = np.empty(N, dtype=np.uint64)
+                lib.orc_mac(_p(o), xp, kp, len(xs), N, int(mod[l]))
+                out[g, c, l] = o
+    return out
+
+
+def polymul(a, b, moduli, nthreads: int = 0) -> np.ndarray:
+    """Negacyclic product through Eq. (1) on data[..., L, N]."""
+    fa = forward(a, moduli, nthreads)
+    fb = forward(b, moduli, nthreads)
+    return inverse(pointwise_mul(fa, fb, moduli), moduli, nthreads)

@@ -1,0 +1,245 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself -- the paper's definitions written independently in big integers, brute
+force on tiny inputs, closed forms, invariants and an independent library
+routine (sympy's linear convolution mod a prime).
+
+Chameleon (arXiv 2410.05934), Sec. II-D: ring R_q = Z_q[x]/(x^N+1); Eq. (1)
+c = INTT_GS(NTT_CT(a) (.) NTT_CT(b)); psi a primitive 2N-th root of unity.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import py_ref
+
+# Primes of every width class the library serves: tiny, 30/32-bit, 50-bit, 60/62-bit.
+SMALL_PRIMES = [17, 97, 257, 7681, 12289]
+WIDE_PRIMES = [
+    998244353,              # 119*2^23 + 1
+    2013265921,             # 15*2^27 + 1
+    4294957057,             # largest q = 1 mod 2^11 below 2^32
+    1125899903827969,       # a q = 1 mod 2^17 just below 2^50
+    4611686018425815041,    # a q = 1 mod 2^17 just below 2^62
+]
+
+
+def _admissible(N, q):
+    return (q - 1) % (2 * N) == 0
+
+
+def _rand(q, n, seed):
+    rng = random.Random(seed)
+    return [rng.randrange(q) for _ in range(n)]
+
+
+# -- number theory ------------------------------------------------------------
+
+def test_is_prime_matches_trial_division():
+    for n in range(0, 20000):
+        assert oracle.is_prime(n) == py_ref.is_prime_trial(n), n
+
+
+def test_is_prime_known_values():
+    for p in [2**61 - 1, 998244353, 2013265921, 18446744073709551557, 4294967291]:
+        assert oracle.is_prime(p)
+    # Carmichael numbers and strong pseudoprimes to several small bases.
+    for c in [561, 41041, 825265, 3215031751, 3825123056546413051, 2**64 - 1, 2**61 + 1]:
+        assert not oracle.is_prime(c)
+
+
+def test_smallest_qnr_bruteforce():
+    primes = [p for p in range(3, 3000) if py_ref.is_prime_trial(p)]
+    for p in primes:
+        assert oracle.smallest_qnr(p) == py_ref.smallest_qnr_bruteforce(p), p
+
+
+@pytest.mark.parametrize("q", SMALL_PRIMES + WIDE_PRIMES)
+def test_psi_is_primitive_2n_root_and_nested(q):
+    N = 1
+    prev = None
+    while _admissible(N, q) and N <= (1 << 16):
+        psi = oracle.psi(N, q)
+        assert psi != 0
+        assert pow(psi, N, q) == q - 1          # psi^N = -1 => order exactly 2N (N a power of 2)
+        assert pow(psi, 2 * N, q) == 1
+        if prev is not None:
+            assert pow(psi, 2, q) == prev       # psi_N = psi_{2N}^2: tables nest across N
+        prev = psi
+        N *= 2
+
+
+def test_psi_rejects_inadmissible():
+    assert oracle.psi(1024, 1000003) == 0           # prime but 2048 does not divide q-1
+    assert oracle.psi(8, 17 * 97) == 0              # composite
+    assert oracle.psi(12, 97) == 0                  # N not a power of two
+
+
+# -- forward / inverse against the definition -----------------------------------
+
+def _cases_small():
+    for q in SMALL_PRIMES + WIDE_PRIMES:
+        for logn in range(1, 7):
+            N = 1 << logn
+            if _admissible(N, q):
+                yield N, q
+
+
+@pytest.mark.parametrize("N,q", list(_cases_small()))
+def test_forward_loop_equals_bigint_definition(N, q):
+    psi = oracle.psi(N, q)
+    a = _rand(q, N, N * 1000 + q % 997)
+    want = py_ref.ntt_definition(a, q, psi)
+    got = oracle.forward(np.array(a, dtype=np.uint64), [q])
+    assert [int(x) for x in got] == want
+    # The C per-output definition agrees as well.
+    assert [oracle.forward_at(np.array(a, dtype=np.uint64), q, j) for j in range(N)] == want
+
+
+@pytest.mark.parametrize("N,q", list(_cases_small()))
+def test_inverse_loop_equals_bigint_definition(N, q):
+    psi = oracle.psi(N, q)
+    ahat = _rand(q, N, N * 77 + q % 991)
+    want = py_ref.intt_definition(ahat, q, psi)
+    got = oracle.inverse(np.array(ahat, dtype=np.uint64), [q])
+    assert [int(x) for x in got] == want
+    assert [oracle.inverse_at(np.array(ahat, dtype=np.uint64), q, i) for i in range(N)] == want
+
+
+@pytest.mark.parametrize("q", [4294957057, 1125899903827969, 4611686018425815041])
+def test_forward_loop_equals_definition_sampled_large(q):
+    N = 1 << 10 if q < (1 << 32) else 1 << 14
+    a = np.array(_rand(q, N, 5), dtype=np.uint64)
+    got = oracle.forward(a, [q])
+    for j in random.Random(1).sample(range(N), 24):
+        assert int(got[j]) == oracle.forward_at(a, q, j)
+
+
+@pytest.mark.parametrize("q", [998244353, 4294957057, 1125899903827969, 4611686018425815041])
+def test_unit_vectors(q):
+    N = 1 << 10
+    psi = oracle.psi(N, q)
+    d0 = np.zeros(N, dtype=np.uint64); d0[0] = 1
+    assert (oracle.forward(d0, [q]) == 1).all()         # constant poly 1 evaluates to 1 everywhere
+    d1 = np.zeros(N, dtype=np.uint64); d1[1] = 1
+    f1 = [int(x) for x in oracle.forward(d1, [q])]
+    # Output j is x evaluated at psi^(2 brv(j) + 1): pins the order and the root.
+    assert f1 == [pow(psi, 2 * py_ref.brv(j, 10) + 1, q) for j in range(N)]
+    # Independent of brv: the outputs are the N distinct roots of x^N + 1 ...
+    assert len(set(f1)) == N and all(pow(r, N, q) == q - 1 for r in f1)
+    # ... and bit-reversed order puts r and -r next to each other.
+    assert all((f1[2 * j] + f1[2 * j + 1]) % q == 0 for j in range(N // 2))
+
+
+@pytest.mark.parametrize("q", [7681, 4294957057, 1125899903827969])
+def test_monomials_closed_form(q):
+    N = 256
+    psi = oracle.psi(N, q)
+    for k in [0, 1, 5, N - 1]:
+        e = np.zeros(N, dtype=np.uint64); e[k] = 1
+        f = [int(x) for x in oracle.forward(e, [q])]
+        assert f == [pow(psi, (2 * py_ref.brv(j, 8) + 1) * k, q) for j in range(N)]
+
+
+@pytest.mark.parametrize("q", [4294957057, 1125899903827969, 4611686018425815041])
+def test_linearity(q):
+    N = 1 << 9
+    a = np.array(_rand(q, N, 11), dtype=np.uint64)
+    b = np.array(_rand(q, N, 12), dtype=np.uint64)
+    al, be = 123456789 % q, (q - 987654321) % q
+    lin = np.array([(al * int(x) + be * int(y)) % q for x, y in zip(a, b)], dtype=np.uint64)
+    fa, fb, fl = (oracle.forward(v, [q]) for v in (a, b, lin))
+    assert [int(x) for x in fl] == [(al * int(x) + be * int(y)) % q for x, y in zip(fa, fb)]
+
+
+@pytest.mark.parametrize("logn", [1, 4, 10, 13, 16])
+@pytest.mark.parametrize("q", [4294957057, 1125899903827969, 4611686018425815041])
+def test_inverse_forward_roundtrip(logn, q):
+    N = 1 << logn
+    if not _admissible(N, q):
+        pytest.skip("q has no 2N-th root for this N")
+    a = np.array(_rand(q, N, logn), dtype=np.uint64)
+    assert (oracle.inverse(oracle.forward(a, [q]), [q]) == a).all()
+    assert (oracle.forward(oracle.inverse(a, [q]), [q]) == a).all()
+
+
+# -- convolution theorem (Eq. 1) against the ring product ----------------------
+
+@pytest.mark.parametrize("N,q", [(n, q) for n, q in _cases_small() if n >= 4])
+def test_polymul_equals_bigint_schoolbook(N, q):
+    a, b = _rand(q, N, 1), _rand(q, N, 2)
+    want = py_ref.negacyclic_schoolbook(a, b, q)
+    got = oracle.polymul(np.array(a, dtype=np.uint64), np.array(b, dtype=np.uint64), [q])
+    assert [int(x) for x in got] == want
+    assert [int(x) for x in oracle.schoolbook(np.array(a, dtype=np.uint64), np.array(b, dtype=np.uint64), q)] == want
+
+
+@pytest.mark.parametrize("logn", [10, 12])
+@pytest.mark.parametrize("q", [4294957057, 1125899903827969, 4611686018425815041])
+def test_polymul_equals_schoolbook_medium(logn, q):
+    N = 1 << logn
+    if not _admissible(N, q):
+        N = 1 << 10
+    a = np.array(_rand(q, N, 3), dtype=np.uint64)
+    b = np.array(_rand(q, N, 4), dtype=np.uint64)
+    got = oracle.polymul(a, b, [q])
+    if logn == 10:
+        assert (got == oracle.schoolbook(a, b, q)).all()
+    else:
+        for k in random.Random(2).sample(range(N), 16):
+            assert int(got[k]) == oracle.negacyclic_at(a, b, q, k)
+
+
+@pytest.mark.parametrize("q", [998244353, 4294957057, 1125899903827969])
+def test_x_to_the_n_is_minus_one(q):
+    N = 1 << 10
+    a = np.zeros(N, dtype=np.uint64); a[N - 1] = 1
+    b = np.zeros(N, dtype=np.uint64); b[1] = 1
+    c = oracle.polymul(a, b, [q])
+    want = np.zeros(N, dtype=np.uint64); want[0] = q - 1
+    assert (c == want).all()
+
+
+def test_polymul_against_sympy_linear_convolution():
+    sympy_discrete = pytest.importorskip("sympy.discrete.convolutions")
+    for q, N in [(998244353, 64), (4294957057, 128), (1125899903827969, 256)]:
+        a, b = _rand(q, N, 21), _rand(q, N, 22)
+        lin = sympy_discrete.convolution_ntt(a, b, prime=q)
+        lin = lin + [0] * (2 * N - len(lin))
+        want = [(lin[k] - lin[k + N]) % q for k in range(N)]
+        got = oracle.polymul(np.array(a, dtype=np.uint64), np.array(b, dtype=np.uint64), [q])
+        assert [int(x) for x in got] == want
+
+
+# -- elementwise ops ------------------------------------------------------------
+
+def test_mac_single_row_is_pointwise_and_sums_rows():
+    q = 4294957057
+    N, rows, cols, P = 64, 3, 2, 7
+    rng = np.random.default_rng(0)
+    a = (rng.integers(0, q, size=(P, 1, N), dtype=np.uint64))
+    k = (rng.integers(0, q, size=(rows, cols, 1, N), dtype=np.uint64))
+    out = oracle.mac(a, k, [q], rows, cols)
+    assert out.shape == (3, cols, 1, N)
+    for g in range(3):
+        for c in range(cols):
+            acc = np.zeros(N, dtype=object)
+            for r in range(rows):
+                p = g * rows + r
+                if p < P:
+                    acc = acc + oracle.pointwise_mul(a[p, 0], k[r, c, 0], [q]).astype(object)
+            assert [int(x) for x in out[g, c, 0]] == [int(v) % q for v in acc]
+    one = oracle.mac(a[:1], k[:1], [q], 1, cols)
+    assert (one[0, 0] == oracle.pointwise_mul(a[0], k[0, 0], [q])).all()
+
+
+def test_batched_layout_rows_use_their_own_modulus():
+    qs = [4294957057, 1125899903827969, 4611686018425815041]
+    N = 1 << 10
+    rng = np.random.default_rng(3)
+    data = np.stack([np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in qs]) for _ in range(2)])
+    f = oracle.forward(data, qs, nthreads=4)
+    for p in range(2):
+        for l, q in enumerate(qs):
+            assert (f[p, l] == oracle.forward(data[p, l], [q], nthreads=1)).all()
