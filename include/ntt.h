@@ -1,0 +1,140 @@
+/*
+ * ntt.h -- C ABI of the MI355X (gfx950) negacyclic NTT library (libntt.so).
+ *
+ * The operation (Chameleon, arXiv 2410.05934, Sec. II-D and Eq. (1)): for a
+ * power-of-two N and a prime q = 1 (mod 2N), the ring R_q = Z_q[x]/(x^N + 1);
+ * the forward transform of a(x) is the Cooley-Tukey NTT taking natural order to
+ * bit-reversed order, out[j] = a(psi^(2*brv(j)+1)) mod q, with psi a primitive
+ * 2N-th root of unity mod q; the inverse is the Gentleman-Sande NTT with
+ * psi^-1, bit-reversed order to natural order, including the factor N^-1; the
+ * product of two polynomials is INTT(NTT(a) (.) NTT(b)).
+ *
+ * Root choice (the paper only requires primitivity): psi = g^((q-1)/(2N)) mod q
+ * with g the smallest quadratic non-residue mod q.  ntt_plan_root() returns it.
+ *
+ * Data layout: a batch of RNS polynomials is one contiguous device array
+ * data[batch][L][N] of uint32_t (word_bits 32) or uint64_t (word_bits 64);
+ * limb l of every polynomial is reduced modulo moduli[l].  Every input must be
+ * canonical, in [0, moduli[l]); every output is canonical.  Out-of-range input
+ * is a precondition violation: the output is then unspecified, but no call
+ * faults on it.
+ *
+ * Ownership: the caller owns every data buffer (device memory, e.g. from a
+ * PyTorch tensor).  A plan owns its device twiddle tables and is read-only
+ * after creation, so one plan may be used from several host threads and
+ * streams at once (polymul at N > 2^12 draws on the plan's own workspace and
+ * serialises itself per plan).  All transform calls are asynchronous on the
+ * given stream (a hipStream_t passed as void*, NULL = the default stream);
+ * their results are valid once the stream has reached that point.
+ *
+ * Errors: every call returns a status code and never aborts; a thread-local
+ * message is available from ntt_last_error().  Calls on an invalid argument
+ * change nothing.
+ */
+#ifndef NTT_MI355X_H
+#define NTT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ntt_plan_s* ntt_plan_t;
+
+typedef enum {
+  NTT_OK = 0,
+  NTT_EINVAL = 1,     /* bad argument: null pointer, N not a power of two in [2, 2^16], word_bits, ... */
+  NTT_ENOTPRIME = 2,  /* a modulus is not prime */
+  NTT_ENOROOT = 3,    /* q != 1 (mod 2N): no primitive 2N-th root of unity */
+  NTT_ERANGE = 4,     /* modulus too wide for the word: q >= 2^32 (32-bit) or q >= 2^62 (64-bit) */
+  NTT_ENOMEM = 5,     /* device or host allocation failed */
+  NTT_EDEVICE = 6,    /* HIP runtime error (no device, launch failure, ...) */
+  NTT_EBUSY = 7,      /* resource in use */
+  NTT_ETIMEOUT = 8    /* a bounded wait inside a persistent launch expired */
+} ntt_status;
+
+/* Plan flags.  NTT_FLAG_SPLIT(n1) forces the pass split N = 2^n1 * 2^(log2 N - n1):
+ * n1 = 0 is a single on-chip pass (N <= 2^14), n1 >= 1 a column pass of n1
+ * stages followed by a row pass (the row part must be 2^4 .. 2^14 words, or
+ * n1 = log2 N for N < 16).  Without it the plan takes the tuned/default split. */
+#define NTT_FLAG_SPLIT(n1) ((uint32_t)(((n1) + 1) & 0x1f) << 8)
+#define NTT_FLAG_SPLIT_MASK (0x1fu << 8)
+/* Force the 64-bit integer (Shoup) arithmetic for every limb, even where the
+ * exact fp64 arithmetic would be chosen (testing and measurement). */
+#define NTT_FLAG_FORCE_INT64 (1u << 16)
+
+/* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
+ * precomputed per modulus as the paper keeps them in constant memory, Sec. II-E).
+ *   N           power of two, 2 <= N <= 65536
+ *   moduli      host array of num_moduli (1 .. 4096) distinct-or-not primes,
+ *               each q = 1 (mod 2N); q < 2^32 for word_bits 32, q < 2^62 for 64
+ *   word_bits   32 or 64: the storage width of every coefficient
+ *   flags       NTT_FLAG_* bits, 0 for defaults
+ * On success *out receives the plan (release with ntt_plan_destroy).  Uses the
+ * current HIP device. */
+ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* moduli,
+                           uint32_t num_moduli, uint32_t word_bits, uint32_t flags);
+
+/* Release a plan and its device tables.  The caller must make sure no work
+ * using the plan is still pending on any stream. */
+ntt_status ntt_plan_destroy(ntt_plan_t plan);
+
+/* The primitive 2N-th root psi used for limb `limb` (see root choice above). */
+ntt_status ntt_plan_root(ntt_plan_t plan, uint32_t limb, uint64_t* psi);
+
+/* The pass split in use: *log_n1 = number of column stages (0 = single pass). */
+ntt_status ntt_plan_split(ntt_plan_t plan, uint32_t* log_n1);
+
+/* Arithmetic class of a limb: 0 = exact fp64 for 32-bit words, 1 = exact fp64
+ * for q < 2^50 - 2^10 in 64-bit words, 2 = 64-bit integer Shoup. */
+ntt_status ntt_plan_limb_class(ntt_plan_t plan, uint32_t limb, uint32_t* cls);
+
+/* Forward NTT in place on data[batch][L][N] (natural -> bit-reversed order). */
+ntt_status ntt_forward(ntt_plan_t plan, void* data, uint32_t batch, void* stream);
+
+/* Inverse NTT in place on data[batch][L][N] (bit-reversed -> natural, times N^-1). */
+ntt_status ntt_inverse(ntt_plan_t plan, void* data, uint32_t batch, void* stream);
+
+/* Eq. (1)'s elementwise product of transformed operands: out = a (.) b mod q_l,
+ * all three [batch][L][N]; out may alias a or b. */
+ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const void* b,
+                             uint32_t batch, void* stream);
+
+/* Grouped multiply-accumulate of transformed operands against a key table (the
+ * MAC of the TFHE external product, Sec. IV-A):
+ *   a     [num_operands][L][N]; operand p is row r = p % rows of group g = p / rows
+ *   key   [rows][cols][L][N]
+ *   out   [groups][cols][L][N], groups = ceil(num_operands / rows)
+ *   out[g][c] = sum over the rows r present in group g of a[g*rows + r] (.) key[r][c]
+ * The last group may be partial.  out must not alias a or key. */
+ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, uint32_t rows,
+                   uint32_t cols, uint32_t num_operands, void* stream);
+
+/* Negacyclic product c = a * b mod (x^N + 1) per limb, through Eq. (1):
+ * out, a, b are [batch][L][N] in natural order; a and b are not modified;
+ * out must not alias a or b. */
+ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,
+                       void* stream);
+
+/* Host-only helpers (no device needed). */
+
+/* Admission check of one modulus for (N, word_bits): NTT_OK or the error a
+ * plan would report for it. */
+ntt_status ntt_check_modulus(uint32_t N, uint64_t q, uint32_t word_bits);
+
+/* The root psi a plan would use for (N, q). */
+ntt_status ntt_find_root(uint32_t N, uint64_t q, uint64_t* psi);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* ntt_last_error(void);
+
+/* Library version string. */
+const char* ntt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTT_MI355X_H */

@@ -1,1 +1,219 @@
-"""MI355X-native negacyclic NTT library (placeholder; binding added next)."""
+"""MI355X-native negacyclic NTT over RNS prime moduli.
+
+A thin ctypes binding of ``libntt.so`` (the C ABI in ``include/ntt.h``).  Every
+step of every transform runs in the library's HIP kernels; this module only
+checks shapes and passes device pointers and the current HIP stream.  PyTorch
+supplies device memory and streams.  There is no CPU fallback: if the library
+is not built, every call raises.
+
+Paper: Chameleon (arXiv 2410.05934), Sec. II-D, Eq. (1) (the transform pair
+and the convolution theorem) and Sec. V (the GPU NTT design this replaces).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
+           "FLAG_FORCE_INT64", "flag_split"]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libntt.so")
+_lock = threading.Lock()
+_lib = None
+
+FLAG_FORCE_INT64 = 1 << 16
+
+STATUS = {0: "NTT_OK", 1: "NTT_EINVAL", 2: "NTT_ENOTPRIME", 3: "NTT_ENOROOT", 4: "NTT_ERANGE",
+          5: "NTT_ENOMEM", 6: "NTT_EDEVICE", 7: "NTT_EBUSY", 8: "NTT_ETIMEOUT"}
+
+
+def flag_split(n1: int) -> int:
+    """NTT_FLAG_SPLIT(n1): force n1 column stages (0 = single pass)."""
+    return ((n1 + 1) & 0x1F) << 8
+
+
+class NTTError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        self.name = STATUS.get(status, f"status {status}")
+        super().__init__(f"{where}: {self.name}: {message}")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_SIGS = {
+    "ntt_plan_create": [ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u64), _u32, _u32, _u32],
+    "ntt_plan_destroy": [_vp],
+    "ntt_plan_root": [_vp, _u32, ctypes.POINTER(_u64)],
+    "ntt_plan_split": [_vp, ctypes.POINTER(_u32)],
+    "ntt_plan_limb_class": [_vp, _u32, ctypes.POINTER(_u32)],
+    "ntt_forward": [_vp, _vp, _u32, _vp],
+    "ntt_inverse": [_vp, _vp, _u32, _vp],
+    "ntt_pointwise_mul": [_vp, _vp, _vp, _vp, _u32, _vp],
+    "ntt_mac": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
+    "ntt_check_modulus": [_u32, _u64, _u32],
+    "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
+}
+
+
+def lib():
+    """Load libntt.so once; raise loudly when it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                                   "`python -c 'import __graft_entry__ as g; g.build()'`")
+            L = ctypes.CDLL(_LIB_PATH)
+            for name, args in _SIGS.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = ctypes.c_int
+            L.ntt_last_error.restype = ctypes.c_char_p
+            L.ntt_last_error.argtypes = []
+            L.ntt_version.restype = ctypes.c_char_p
+            L.ntt_version.argtypes = []
+            _lib = L
+    return _lib
+
+
+def _check(st: int, where: str) -> None:
+    if st != 0:
+        msg = lib().ntt_last_error().decode(errors="replace")
+        raise NTTError(st, where, msg)
+
+
+def check_modulus(N: int, q: int, word_bits: int) -> int:
+    """Status code a plan would report for (N, q, word_bits); 0 = admissible."""
+    return int(lib().ntt_check_modulus(N, q, word_bits))
+
+
+def find_root(N: int, q: int) -> int:
+    out = _u64()
+    _check(lib().ntt_find_root(N, q, ctypes.byref(out)), "ntt_find_root")
+    return int(out.value)
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """An NTT plan: length N, RNS moduli, word width; owns device twiddle tables.
+
+    Tensors passed to the methods are contiguous CUDA (HIP) tensors of shape
+    [batch, L, N] (or anything with batch*L*N elements) whose element size
+    equals word_bits/8; torch.int64 / torch.int32 tensors hold the uint64 /
+    uint32 words bit for bit.
+    """
+
+    def __init__(self, N: int, moduli, word_bits: int = 64, flags: int = 0):
+        self.N = int(N)
+        self.moduli = [int(q) for q in moduli]
+        self.L = len(self.moduli)
+        self.word_bits = int(word_bits)
+        arr = (_u64 * self.L)(*self.moduli)
+        h = _vp()
+        _check(lib().ntt_plan_create(ctypes.byref(h), self.N, arr, self.L, self.word_bits, flags),
+               "ntt_plan_create")
+        self._h = h
+
+    # -- queries -------------------------------------------------------------
+    def root(self, limb: int) -> int:
+        out = _u64()
+        _check(lib().ntt_plan_root(self._h, limb, ctypes.byref(out)), "ntt_plan_root")
+        return int(out.value)
+
+    @property
+    def split(self) -> int:
+        out = _u32()
+        _check(lib().ntt_plan_split(self._h, ctypes.byref(out)), "ntt_plan_split")
+        return int(out.value)
+
+    def limb_class(self, limb: int) -> int:
+        out = _u32()
+        _check(lib().ntt_plan_limb_class(self._h, limb, ctypes.byref(out)), "ntt_plan_limb_class")
+        return int(out.value)
+
+    @property
+    def handle(self) -> int:
+        return int(self._h.value)
+
+    # -- helpers -------------------------------------------------------------
+    def _batch_of(self, t, name: str) -> int:
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.element_size() * 8 != self.word_bits:
+            raise ValueError(f"{name} element size {t.element_size()} does not match word_bits {self.word_bits}")
+        per = self.L * self.N
+        if t.numel() == 0 or t.numel() % per:
+            raise ValueError(f"{name} has {t.numel()} elements, not a multiple of L*N={per}")
+        return t.numel() // per
+
+    # -- operations ----------------------------------------------------------
+    def forward(self, x, stream=None):
+        """In-place forward NTT of x[batch][L][N]; returns x."""
+        b = self._batch_of(x, "x")
+        _check(lib().ntt_forward(self._h, x.data_ptr(), b, _stream_handle(stream)), "ntt_forward")
+        return x
+
+    def inverse(self, x, stream=None):
+        b = self._batch_of(x, "x")
+        _check(lib().ntt_inverse(self._h, x.data_ptr(), b, _stream_handle(stream)), "ntt_inverse")
+        return x
+
+    def pointwise_mul(self, out, a, b, stream=None):
+        n = self._batch_of(out, "out")
+        if self._batch_of(a, "a") != n or self._batch_of(b, "b") != n:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_pointwise_mul(self._h, out.data_ptr(), a.data_ptr(), b.data_ptr(), n,
+                                       _stream_handle(stream)), "ntt_pointwise_mul")
+        return out
+
+    def mac(self, out, a, key, rows: int, cols: int, stream=None):
+        P = self._batch_of(a, "a")
+        groups = (P + rows - 1) // rows
+        if self._batch_of(key, "key") != rows * cols:
+            raise ValueError("key must hold rows*cols polynomials")
+        if self._batch_of(out, "out") != groups * cols:
+            raise ValueError("out must hold ceil(P/rows)*cols polynomials")
+        _check(lib().ntt_mac(self._h, out.data_ptr(), a.data_ptr(), key.data_ptr(), rows, cols, P,
+                             _stream_handle(stream)), "ntt_mac")
+        return out
+
+    def polymul(self, out, a, b, stream=None):
+        n = self._batch_of(out, "out")
+        if self._batch_of(a, "a") != n or self._batch_of(b, "b") != n:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_polymul(self._h, out.data_ptr(), a.data_ptr(), b.data_ptr(), n,
+                                 _stream_handle(stream)), "ntt_polymul")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ntt_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,13 @@
+// inst_f64l.hip -- kernels and launchers of the ArF64L arithmetic class.
+#include "ntt_launch.hpp"
+
+namespace nttk {
+template hipError_t transform_cls<ArF64L>(const ntt_plan_s*, int, void*, uint32_t, bool,
+                                         hipStream_t);
+template hipError_t pointwise_cls<ArF64L>(const ntt_plan_s*, int, void*, const void*, const void*,
+                                         uint32_t, hipStream_t);
+template hipError_t polymul_cls<ArF64L>(const ntt_plan_s*, int, void*, const void*, const void*,
+                                       void*, uint32_t, hipStream_t);
+template hipError_t mac_cls<ArF64L>(const ntt_plan_s*, int, void*, const void*, const void*,
+                                   uint32_t, uint32_t, uint32_t, hipStream_t);
+}  // namespace nttk

@@ -1,0 +1,543 @@
+// ntt_kernels.hpp -- gfx950 kernels for the negacyclic NTT over RNS limbs.
+//
+// Transform structure (Chameleon, Sec. II-D, Eq. (1)): the forward transform is
+// the Cooley-Tukey network taking natural order to bit-reversed order with
+// twiddles psi^brv(m+i); the inverse is the Gentleman-Sande network taking
+// bit-reversed order back to natural order with psi^-brv(m+i), followed by
+// N^-1 (folded here into the last stage).  Stage s (s = 0 .. log2 N - 1) has
+// m = 2^s groups; element x pairs with x + N/2^(s+1), twiddle index
+// 2^s + (x >> (log2 N - s)).
+//
+// Splitting N = N1 * N2 (the paper's two-phase hybrid, Sec. V-C/V-D):
+//   column pass   stages 0 .. log2 N1 - 1.  For a fixed r in [0, N2) the
+//                 elements {r + k*N2} are closed under these stages.  One
+//                 thread owns one column: it loads its N1 elements (lanes own
+//                 consecutive r, so every load is coalesced), runs all of the
+//                 column's stages in registers and stores them back.  The
+//                 twiddles psi^brv(1 .. N1-1) are the same for every column.
+//   row pass      stages log2 N1 .. log2 N - 1.  Each contiguous chunk of N2
+//                 words is closed under these stages.  One chunk is owned by
+//                 N2/16 threads holding 16 values each; rounds of four fused
+//                 stages run in registers (radix-16), and the values are
+//                 re-dealt between rounds through padded LDS.  The first
+//                 forward round deals out the top four index bits, so global
+//                 loads are coalesced; the last round holds the bottom four
+//                 bits, i.e. 16 consecutive words per thread (one 128-byte line
+//                 for 64-bit words).
+// N <= 2^14 runs as a single row pass (N1 = 1).  Tiny N < 16 runs as a single
+// column pass (N2 = 1).  The split is a plan parameter (autotuned).
+//
+// This replaces the paper's butterfly decomposition / thread aggregation /
+// coefficient shuffling with the wave64 form of the same ideas: a thread owns
+// whole radix-16 sub-transforms (thread aggregation), the data layout keeps
+// every dependent value inside one workgroup (coefficient shuffling), and the
+// only global synchronisation is the pass boundary.
+#pragma once
+
+#include "modarith.hpp"
+
+namespace nttk {
+
+constexpr int kRowThreadsMin = 256;
+
+struct RowArgs {
+  void* dst;                 // output (row pass writes here)
+  const void* src;           // input (may equal dst)
+  const void* src2;          // second input (fused polymul only)
+  const LimbDev* limbs;      // [L]
+  const uint32_t* cls_limbs; // limb indices handled by this launch
+  uint32_t n_cls;            // number of entries in cls_limbs
+  uint32_t L;                // limbs per polynomial in the data layout
+  uint32_t log_n;            // log2 N
+  uint32_t log_n1;           // column stages before this pass (0: single pass)
+  uint32_t total_chunks;     // batch * n_cls * N1
+};
+
+struct ColArgs {
+  void* dst;
+  const void* src;
+  const LimbDev* limbs;
+  const uint32_t* cls_limbs;
+  uint32_t n_cls;
+  uint32_t L;
+  uint32_t log_n;
+  uint32_t log_n2;           // row stages after this pass (0: whole transform)
+  uint32_t total_cols;       // batch * n_cls * N2
+};
+
+struct EltArgs {
+  void* dst;
+  const void* a;
+  const void* b;
+  const LimbDev* limbs;
+  const uint32_t* cls_limbs;
+  uint32_t n_cls;
+  uint32_t L;
+  uint32_t log_n;
+  uint64_t total;            // batch * n_cls * N elements
+};
+
+struct MacArgs {
+  void* dst;                 // [groups][cols][L][N]
+  const void* a;             // [num_operands][L][N]
+  const void* key;           // [rows][cols][L][N]
+  const LimbDev* limbs;
+  const uint32_t* cls_limbs;
+  uint32_t n_cls;
+  uint32_t L;
+  uint32_t log_n;
+  uint32_t rows, cols, num_operands, groups;
+  uint64_t total;            // groups * n_cls * N
+};
+
+template <int LOGN2>
+struct RowShape {
+  static constexpr int N2 = 1 << LOGN2;
+  static constexpr int TPC = N2 / 16;  // threads per chunk
+  static constexpr int CPW = TPC >= kRowThreadsMin ? 1 : kRowThreadsMin / TPC;
+  static constexpr int BLOCK = TPC * CPW;
+  static constexpr int K = (LOGN2 + 3) / 4;  // radix-16 rounds
+  static constexpr int LAST = LOGN2 - 4 * (K - 1);  // stages in the last round
+  static constexpr int CHUNK_LDS = K > 1 ? N2 + N2 / 16 : 1;
+  static constexpr int LDS_ELEMS = CPW * CHUNK_LDS;
+  // held-bit offset of round j (forward numbering)
+  static constexpr int hb(int j) { return j < K - 1 ? LOGN2 - 4 - 4 * j : 0; }
+  static constexpr int nst(int j) { return j < K - 1 ? 4 : LAST; }
+};
+
+__device__ __forceinline__ uint32_t ins_bits(uint32_t tt, uint32_t u, int hb) {
+  return ((tt >> hb) << (hb + 4)) | (u << hb) | (tt & ((1u << hb) - 1u));
+}
+__device__ __forceinline__ uint32_t lds_pad(uint32_t y) { return y + (y >> 4); }
+
+// Load G consecutive twiddles starting at an index that is a multiple of G.
+template <class TW, int G>
+__device__ __forceinline__ void load_tw(TW (&w)[G], const TW* __restrict__ tab, uint32_t idx) {
+  if constexpr (sizeof(TW) == 8 && G >= 2) {
+    const double2* p = reinterpret_cast<const double2*>(tab + idx);
+#pragma unroll
+    for (int i = 0; i < G / 2; ++i) {
+      const double2 t = p[i];
+      w[2 * i] = t.x;
+      w[2 * i + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < G; ++i) w[i] = tab[idx + i];
+  }
+}
+
+// One forward (CT) stage on the 16 registers: local stage SP acts on u-bit B.
+template <class A, int B, int SP, int HB>
+__device__ __forceinline__ void fwd_stage(const A& ar, typename A::V (&v)[16],
+                                          const typename A::TW* __restrict__ tw, uint32_t base,
+                                          uint32_t tt) {
+  constexpr int G = 1 << (3 - B);
+  typename A::TW w[G];
+  const uint32_t tg = (base << SP) + ((tt >> HB) << (3 - B));
+  load_tw<typename A::TW, G>(w, tw, tg);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int i = 0; i < (1 << B); ++i) {
+      const int lo = (g << (B + 1)) | i;
+      ar.ct(v[lo], v[lo | (1 << B)], w[g]);
+    }
+  }
+}
+
+// One inverse (GS) stage; FOLD applies N^-1 (only for global stage 0).
+template <class A, int B, int SP, int HB, bool FOLD>
+__device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[16],
+                                          const typename A::TW* __restrict__ tw, uint32_t base,
+                                          uint32_t tt, const LimbDev& ld) {
+  constexpr int G = 1 << (3 - B);
+  if constexpr (FOLD) {
+    static_assert(G == 1, "fold only at the single-group stage");
+#pragma unroll
+    for (int i = 0; i < (1 << B); ++i) {
+      typename A::TW w{};
+      ar.gs_fold(v[i], v[i | (1 << B)], w, ld);
+    }
+  } else {
+    typename A::TW w[G];
+    const uint32_t tg = (base << SP) + ((tt >> HB) << (3 - B));
+    load_tw<typename A::TW, G>(w, tw, tg);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int i = 0; i < (1 << B); ++i) {
+        const int lo = (g << (B + 1)) | i;
+        ar.gs(v[lo], v[lo | (1 << B)], w[g]);
+      }
+    }
+  }
+}
+
+template <class A, int LOGN2, int J, int ST>
+__device__ __forceinline__ void fwd_round_stages(const A& ar, typename A::V (&v)[16],
+                                                 const typename A::TW* __restrict__ tw,
+                                                 uint32_t base, uint32_t tt) {
+  using S = RowShape<LOGN2>;
+  if constexpr (ST < S::nst(J)) {
+    constexpr int HB = S::hb(J);
+    constexpr int SP = 4 * J + ST;
+    constexpr int B = (LOGN2 - 1 - SP) - HB;
+    fwd_stage<A, B, SP, HB>(ar, v, tw, base, tt);
+    fwd_round_stages<A, LOGN2, J, ST + 1>(ar, v, tw, base, tt);
+  }
+}
+
+// Inverse stages of round J run from the highest local stage down.
+template <class A, int LOGN2, int J, int ST, bool FOLD>
+__device__ __forceinline__ void inv_round_stages(const A& ar, typename A::V (&v)[16],
+                                                 const typename A::TW* __restrict__ tw,
+                                                 uint32_t base, uint32_t tt, const LimbDev& ld) {
+  using S = RowShape<LOGN2>;
+  if constexpr (ST < S::nst(J)) {
+    constexpr int HB = S::hb(J);
+    constexpr int SP = 4 * J + S::nst(J) - 1 - ST;
+    constexpr int B = (LOGN2 - 1 - SP) - HB;
+    if constexpr (FOLD && SP == 0) {
+      inv_stage<A, B, SP, HB, true>(ar, v, tw, base, tt, ld);
+    } else {
+      inv_stage<A, B, SP, HB, false>(ar, v, tw, base, tt, ld);
+    }
+    inv_round_stages<A, LOGN2, J, ST + 1, FOLD>(ar, v, tw, base, tt, ld);
+  }
+}
+
+// Re-deal 16 values per thread from the layout of round JF to round JT.
+template <class A, int LOGN2, int JF, int JT>
+__device__ __forceinline__ void lds_exchange(typename A::V (&v)[16], typename A::V* lds,
+                                             uint32_t tt) {
+  using S = RowShape<LOGN2>;
+  constexpr int HF = S::hb(JF), HT = S::hb(JT);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) lds[lds_pad(ins_bits(tt, u, HF))] = v[u];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = lds[lds_pad(ins_bits(tt, u, HT))];
+  __syncthreads();
+}
+
+template <class A, int LOGN2, int J>
+__device__ __forceinline__ void row_forward_from(const A& ar, typename A::V (&v)[16],
+                                                 const typename A::TW* __restrict__ tw,
+                                                 uint32_t base, uint32_t tt, typename A::V* lds) {
+  using S = RowShape<LOGN2>;
+  if constexpr (J < S::K) {
+    fwd_round_stages<A, LOGN2, J, 0>(ar, v, tw, base, tt);
+    if constexpr (J + 1 < S::K) {
+      if constexpr (A::kCenterRounds) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ar.center(v[u]);
+      }
+      lds_exchange<A, LOGN2, J, J + 1>(v, lds, tt);
+      row_forward_from<A, LOGN2, J + 1>(ar, v, tw, base, tt, lds);
+    }
+  }
+}
+
+template <class A, int LOGN2, int J, bool FOLD>
+__device__ __forceinline__ void row_inverse_from(const A& ar, typename A::V (&v)[16],
+                                                 const typename A::TW* __restrict__ tw,
+                                                 uint32_t base, uint32_t tt, typename A::V* lds,
+                                                 const LimbDev& ld) {
+  if constexpr (J >= 0) {
+    inv_round_stages<A, LOGN2, J, 0, FOLD>(ar, v, tw, base, tt, ld);
+    if constexpr (J > 0) {
+      if constexpr (A::kCenterRounds) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ar.center(v[u]);
+      }
+      lds_exchange<A, LOGN2, J, J - 1>(v, lds, tt);
+      row_inverse_from<A, LOGN2, J - 1, FOLD>(ar, v, tw, base, tt, lds, ld);
+    }
+  }
+}
+
+// Chunk bookkeeping shared by the row kernels.
+struct ChunkPos {
+  uint64_t off;     // word offset of the chunk
+  uint32_t limb;
+  uint32_t base;    // (N1 + c): twiddle base of this chunk
+  bool valid;
+};
+
+__device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int log_n2) {
+  ChunkPos p;
+  p.valid = gc < a.total_chunks;
+  const uint32_t g = p.valid ? gc : 0;
+  const uint32_t n1 = 1u << a.log_n1;
+  const uint32_t c = g & (n1 - 1);
+  const uint32_t rest = g >> a.log_n1;
+  const uint32_t li = rest % a.n_cls;
+  const uint32_t poly = rest / a.n_cls;
+  p.limb = a.cls_limbs[li];
+  p.off = ((uint64_t)poly * a.L + p.limb) << a.log_n;
+  p.off += (uint64_t)c << log_n2;
+  p.base = n1 + c;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Row pass.  INV selects the transform direction; TWO_PASS says whether a
+// column pass precedes (forward) or follows (inverse) this kernel.
+template <class A, int LOGN2, bool INV, bool TWO_PASS>
+__global__ void __launch_bounds__(RowShape<LOGN2>::BLOCK)
+row_kernel(RowArgs args) {
+  using S = RowShape<LOGN2>;
+  using V = typename A::V;
+  using W = typename A::W;
+  __shared__ V lds_all[S::LDS_ELEMS];
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+  const ChunkPos cp = chunk_pos(args, blockIdx.x * S::CPW + ci, LOGN2);
+  const LimbDev& ld = args.limbs[cp.limb];
+  const A ar(ld);
+  V* lds = lds_all + ci * S::CHUNK_LDS;
+  const W* __restrict__ src = reinterpret_cast<const W*>(args.src) + cp.off;
+  W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + cp.off;
+  V v[16];
+  if constexpr (!INV) {
+    constexpr int H0 = S::hb(0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const W x = cp.valid ? src[ins_bits(tt, u, H0)] : W(0);
+      v[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
+    }
+    const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twf);
+    row_forward_from<A, LOGN2, 0>(ar, v, tw, cp.base, tt, lds);
+    constexpr int HL = S::hb(S::K - 1);
+    if (cp.valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) dst[ins_bits(tt, u, HL)] = ar.to_word(v[u]);
+    }
+  } else {
+    constexpr int HL = S::hb(S::K - 1);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const W x = cp.valid ? src[ins_bits(tt, u, HL)] : W(0);
+      v[u] = ar.from_word(x);
+      ar.center(v[u]);
+    }
+    const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twi);
+    row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, v, tw, cp.base, tt, lds, ld);
+    constexpr int H0 = S::hb(0);
+    if (cp.valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        dst[ins_bits(tt, u, H0)] = TWO_PASS ? ar.to_raw(v[u]) : ar.to_word(v[u]);
+    }
+  }
+}
+
+// Fused negacyclic product on one row chunk: forward(a), forward(b), pointwise
+// product, inverse -- Eq. (1) without leaving registers/LDS.  With TWO_PASS
+// the inputs are column-pass outputs and the result still needs the inverse
+// column pass.
+template <class A, int LOGN2, bool TWO_PASS>
+__global__ void __launch_bounds__(RowShape<LOGN2>::BLOCK)
+polymul_row_kernel(RowArgs args) {
+  using S = RowShape<LOGN2>;
+  using V = typename A::V;
+  using W = typename A::W;
+  __shared__ V lds_all[S::LDS_ELEMS];
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+  const ChunkPos cp = chunk_pos(args, blockIdx.x * S::CPW + ci, LOGN2);
+  const LimbDev& ld = args.limbs[cp.limb];
+  const A ar(ld);
+  V* lds = lds_all + ci * S::CHUNK_LDS;
+  const W* __restrict__ sa = reinterpret_cast<const W*>(args.src) + cp.off;
+  const W* __restrict__ sb = reinterpret_cast<const W*>(args.src2) + cp.off;
+  W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + cp.off;
+  const auto* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
+  const auto* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
+  constexpr int H0 = S::hb(0);
+  V va[16], vb[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const W x = cp.valid ? sa[ins_bits(tt, u, H0)] : W(0);
+    va[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
+  }
+  row_forward_from<A, LOGN2, 0>(ar, va, twf, cp.base, tt, lds);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const W x = cp.valid ? sb[ins_bits(tt, u, H0)] : W(0);
+    vb[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
+  }
+  row_forward_from<A, LOGN2, 0>(ar, vb, twf, cp.base, tt, lds);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    va[u] = ar.mul(va[u], vb[u]);
+    ar.center(va[u]);
+  }
+  row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, va, twi, cp.base, tt, lds, ld);
+  if (cp.valid) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      dst[ins_bits(tt, u, H0)] = TWO_PASS ? ar.to_raw(va[u]) : ar.to_word(va[u]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: one thread owns one column of N1 = 2^LOGN1 elements.
+constexpr int kColBlock = 256;
+
+template <class A, int LOGN1, bool INV, bool TWO_PASS>
+__global__ void __launch_bounds__(kColBlock)
+col_kernel(ColArgs args) {
+  using V = typename A::V;
+  using W = typename A::W;
+  using TW = typename A::TW;
+  constexpr int N1 = 1 << LOGN1;
+  const uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
+  const bool valid = gid < args.total_cols;
+  const uint32_t g = valid ? gid : 0;
+  const uint32_t n2 = 1u << args.log_n2;
+  const uint32_t r = g & (n2 - 1);
+  const uint32_t rest = g >> args.log_n2;
+  const uint32_t li = rest % args.n_cls;
+  const uint32_t poly = rest / args.n_cls;
+  const uint32_t limb = args.cls_limbs[li];
+  const LimbDev& ld = args.limbs[limb];
+  const A ar(ld);
+  const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
+  const W* __restrict__ src = reinterpret_cast<const W*>(args.src) + off;
+  W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + off;
+  V v[N1];
+  if constexpr (!INV) {
+    const TW* __restrict__ tw = reinterpret_cast<const TW*>(ld.twf);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const W x = valid ? src[(uint64_t)k << args.log_n2] : W(0);
+      v[k] = ar.from_word(x);
+    }
+#pragma unroll
+    for (int s = 0; s < LOGN1; ++s) {
+      const int t = N1 >> (s + 1);
+#pragma unroll
+      for (int i = 0; i < (1 << s); ++i) {
+        const TW w = tw[(1 << s) + i];
+#pragma unroll
+        for (int j = 0; j < t; ++j) ar.ct(v[2 * i * t + j], v[2 * i * t + j + t], w);
+      }
+      if constexpr (A::kCenterRounds) {
+        if ((s & 3) == 3 && s + 1 < LOGN1) {
+#pragma unroll
+          for (int k = 0; k < N1; ++k) ar.center(v[k]);
+        }
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < N1; ++k)
+        dst[(uint64_t)k << args.log_n2] = TWO_PASS ? ar.to_raw(v[k]) : ar.to_word(v[k]);
+    }
+  } else {
+    const TW* __restrict__ tw = reinterpret_cast<const TW*>(ld.twi);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const W x = valid ? src[(uint64_t)k << args.log_n2] : W(0);
+      v[k] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
+      ar.center(v[k]);
+    }
+#pragma unroll
+    for (int s = LOGN1 - 1; s >= 0; --s) {
+      const int t = N1 >> (s + 1);
+      if (s == 0) {
+        TW w{};
+#pragma unroll
+        for (int j = 0; j < t; ++j) ar.gs_fold(v[j], v[j + t], w, ld);
+      } else {
+#pragma unroll
+        for (int i = 0; i < (1 << s); ++i) {
+          const TW w = tw[(1 << s) + i];
+#pragma unroll
+          for (int j = 0; j < t; ++j) ar.gs(v[2 * i * t + j], v[2 * i * t + j + t], w);
+        }
+      }
+      if constexpr (A::kCenterRounds) {
+        if (((LOGN1 - 1 - s) & 3) == 3 && s > 0) {
+#pragma unroll
+          for (int k = 0; k < N1; ++k) ar.center(v[k]);
+        }
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < N1; ++k) dst[(uint64_t)k << args.log_n2] = ar.to_word(v[k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise product c = a (.) b on [batch][L][N] (NTT domain).
+constexpr int kEltBlock = 256;
+
+template <class A>
+__global__ void __launch_bounds__(kEltBlock)
+pointwise_kernel(EltArgs args) {
+  using W = typename A::W;
+  const uint64_t n = 1ull << args.log_n;
+  for (uint64_t i = blockIdx.x * (uint64_t)kEltBlock + threadIdx.x; i < args.total;
+       i += (uint64_t)gridDim.x * kEltBlock) {
+    const uint64_t j = i & (n - 1);
+    const uint64_t rest = i >> args.log_n;
+    const uint32_t li = (uint32_t)(rest % args.n_cls);
+    const uint64_t poly = rest / args.n_cls;
+    const uint32_t limb = args.cls_limbs[li];
+    const LimbDev& ld = args.limbs[limb];
+    const A ar(ld);
+    const uint64_t off = ((poly * args.L + limb) << args.log_n) + j;
+    const W x = reinterpret_cast<const W*>(args.a)[off];
+    const W y = reinterpret_cast<const W*>(args.b)[off];
+    reinterpret_cast<W*>(args.dst)[off] = ar.to_word(ar.mul(ar.from_word(x), ar.from_word(y)));
+  }
+}
+
+// Grouped multiply-accumulate (external-product MAC in the NTT domain):
+// out[g][c] = sum over rows r present in group g of a[g*rows + r] (.) key[r][c].
+template <class A>
+__global__ void __launch_bounds__(kEltBlock)
+mac_kernel(MacArgs args) {
+  using W = typename A::W;
+  using V = typename A::V;
+  const uint64_t n = 1ull << args.log_n;
+  for (uint64_t i = blockIdx.x * (uint64_t)kEltBlock + threadIdx.x; i < args.total;
+       i += (uint64_t)gridDim.x * kEltBlock) {
+    const uint64_t j = i & (n - 1);
+    const uint64_t rest = i >> args.log_n;
+    const uint32_t li = (uint32_t)(rest % args.n_cls);
+    const uint32_t grp = (uint32_t)(rest / args.n_cls);
+    const uint32_t limb = args.cls_limbs[li];
+    const LimbDev& ld = args.limbs[limb];
+    const A ar(ld);
+    const W* a = reinterpret_cast<const W*>(args.a);
+    const W* key = reinterpret_cast<const W*>(args.key);
+    W* out = reinterpret_cast<W*>(args.dst);
+    const uint64_t limb_off = ((uint64_t)limb << args.log_n) + j;
+    for (uint32_t c = 0; c < args.cols; ++c) {
+      V acc{};
+      bool first = true;
+      for (uint32_t r = 0; r < args.rows; ++r) {
+        const uint32_t p = grp * args.rows + r;
+        if (p >= args.num_operands) break;
+        const V x = ar.from_word(a[(uint64_t)p * args.L * n + limb_off]);
+        const V k = ar.from_word(key[((uint64_t)r * args.cols + c) * args.L * n + limb_off]);
+        const V prod = ar.mul(x, k);
+        if (first) {
+          acc = prod;
+          first = false;
+        } else {
+          acc = ar.add(acc, prod);
+        }
+      }
+      out[((uint64_t)grp * args.cols + c) * args.L * n + limb_off] = ar.to_word(acc);
+    }
+  }
+}
+
+}  // namespace nttk

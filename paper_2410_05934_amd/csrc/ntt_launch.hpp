@@ -1,0 +1,217 @@
+// ntt_launch.hpp -- host launchers for the kernels of one arithmetic class.
+// Included by one translation unit per class (inst_*.hip), which instantiates
+// them explicitly, so the three classes compile in parallel.
+#pragma once
+
+#include <algorithm>
+
+#include "ntt_internal.hpp"
+#include "ntt_kernels.hpp"
+
+namespace nttk {
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+template <class A, int LOGN2, bool INV, bool TWO>
+hipError_t launch_row_n(const RowArgs& a, hipStream_t s) {
+  using S = RowShape<LOGN2>;
+  const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
+  hipLaunchKernelGGL((row_kernel<A, LOGN2, INV, TWO>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class A, int LOGN2, bool TWO>
+hipError_t launch_pm_n(const RowArgs& a, hipStream_t s) {
+  using S = RowShape<LOGN2>;
+  const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
+  hipLaunchKernelGGL((polymul_row_kernel<A, LOGN2, TWO>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class A, int LOGN1, bool INV, bool TWO>
+hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
+  const uint32_t blocks = (a.total_cols + kColBlock - 1) / kColBlock;
+  hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(kColBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class A, bool INV, bool TWO>
+hipError_t launch_row(int logn2, const RowArgs& a, hipStream_t s) {
+  switch (logn2) {
+    case 4: return launch_row_n<A, 4, INV, TWO>(a, s);
+    case 5: return launch_row_n<A, 5, INV, TWO>(a, s);
+    case 6: return launch_row_n<A, 6, INV, TWO>(a, s);
+    case 7: return launch_row_n<A, 7, INV, TWO>(a, s);
+    case 8: return launch_row_n<A, 8, INV, TWO>(a, s);
+    case 9: return launch_row_n<A, 9, INV, TWO>(a, s);
+    case 10: return launch_row_n<A, 10, INV, TWO>(a, s);
+    case 11: return launch_row_n<A, 11, INV, TWO>(a, s);
+    case 12: return launch_row_n<A, 12, INV, TWO>(a, s);
+    case 13: return launch_row_n<A, 13, INV, TWO>(a, s);
+    case 14: return launch_row_n<A, 14, INV, TWO>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class A, bool TWO>
+hipError_t launch_pm(int logn2, const RowArgs& a, hipStream_t s) {
+  switch (logn2) {
+    case 4: return launch_pm_n<A, 4, TWO>(a, s);
+    case 5: return launch_pm_n<A, 5, TWO>(a, s);
+    case 6: return launch_pm_n<A, 6, TWO>(a, s);
+    case 7: return launch_pm_n<A, 7, TWO>(a, s);
+    case 8: return launch_pm_n<A, 8, TWO>(a, s);
+    case 9: return launch_pm_n<A, 9, TWO>(a, s);
+    case 10: return launch_pm_n<A, 10, TWO>(a, s);
+    case 11: return launch_pm_n<A, 11, TWO>(a, s);
+    case 12: return launch_pm_n<A, 12, TWO>(a, s);
+    case 13: return launch_pm_n<A, 13, TWO>(a, s);
+    case 14: return launch_pm_n<A, 14, TWO>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class A, bool INV, bool TWO>
+hipError_t launch_col(int logn1, const ColArgs& a, hipStream_t s) {
+  switch (logn1) {
+    case 1: return launch_col_n<A, 1, INV, TWO>(a, s);
+    case 2: return launch_col_n<A, 2, INV, TWO>(a, s);
+    case 3: return launch_col_n<A, 3, INV, TWO>(a, s);
+    case 4: return launch_col_n<A, 4, INV, TWO>(a, s);
+    case 5: return launch_col_n<A, 5, INV, TWO>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline RowArgs row_args(const ntt_plan_s* p, int c, void* dst, const void* src, const void* src2,
+                        uint32_t batch) {
+  RowArgs a;
+  a.dst = dst;
+  a.src = src;
+  a.src2 = src2;
+  a.limbs = p->d_limbs;
+  a.cls_limbs = p->d_cls_limbs + p->cls_off[c];
+  a.n_cls = p->cls_cnt[c];
+  a.L = p->L;
+  a.log_n = p->log_n;
+  a.log_n1 = p->log_n1;
+  a.total_chunks = batch * p->cls_cnt[c] << p->log_n1;
+  return a;
+}
+
+inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, uint32_t batch) {
+  ColArgs a;
+  a.dst = dst;
+  a.src = src;
+  a.limbs = p->d_limbs;
+  a.cls_limbs = p->d_cls_limbs + p->cls_off[c];
+  a.n_cls = p->cls_cnt[c];
+  a.L = p->L;
+  a.log_n = p->log_n;
+  a.log_n2 = p->log_n - p->log_n1;
+  a.total_cols = (batch * p->cls_cnt[c]) << a.log_n2;
+  return a;
+}
+
+template <class A>
+hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
+                                hipStream_t s) {
+  const int n = p->log_n, n1 = p->log_n1, n2 = n - n1;
+  hipError_t e = hipSuccess;
+  if (n1 == 0) {
+    RowArgs a = row_args(p, c, data, data, nullptr, batch);
+    e = inv ? launch_row<A, true, false>(n2, a, s) : launch_row<A, false, false>(n2, a, s);
+  } else if (n2 == 0) {
+    ColArgs a = col_args(p, c, data, data, batch);
+    e = inv ? launch_col<A, true, false>(n1, a, s) : launch_col<A, false, false>(n1, a, s);
+  } else if (!inv) {
+    ColArgs ca = col_args(p, c, data, data, batch);
+    e = launch_col<A, false, true>(n1, ca, s);
+    if (e == hipSuccess) {
+      RowArgs ra = row_args(p, c, data, data, nullptr, batch);
+      e = launch_row<A, false, true>(n2, ra, s);
+    }
+  } else {
+    RowArgs ra = row_args(p, c, data, data, nullptr, batch);
+    e = launch_row<A, true, true>(n2, ra, s);
+    if (e == hipSuccess) {
+      ColArgs ca = col_args(p, c, data, data, batch);
+      e = launch_col<A, true, true>(n1, ca, s);
+    }
+  }
+  return e;
+}
+
+template <class A>
+hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a,
+                                const void* b, uint32_t batch, hipStream_t s) {
+  EltArgs ea;
+  ea.dst = out;
+  ea.a = a;
+  ea.b = b;
+  ea.limbs = p->d_limbs;
+  ea.cls_limbs = p->d_cls_limbs + p->cls_off[c];
+  ea.n_cls = p->cls_cnt[c];
+  ea.L = p->L;
+  ea.log_n = p->log_n;
+  ea.total = ((uint64_t)batch * p->cls_cnt[c]) << p->log_n;
+  const uint64_t want = (ea.total + kEltBlock - 1) / kEltBlock;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256ull * 64);
+  hipLaunchKernelGGL((pointwise_kernel<A>), dim3(blocks), dim3(kEltBlock), 0, s, ea);
+  return hipGetLastError();
+}
+
+template <class A>
+hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
+                              void* ws, uint32_t batch, hipStream_t s) {
+  const int n = p->log_n, n1 = p->log_n1, n2 = n - n1;
+  hipError_t e;
+  if (n1 == 0) {
+    RowArgs ra = row_args(p, c, out, a, b, batch);
+    return launch_pm<A, false>(n2, ra, s);
+  }
+  if (n2 == 0) {
+    // Tiny N: forward both into out / ws, multiply, inverse.
+    ColArgs ca = col_args(p, c, out, a, batch);
+    if ((e = launch_col<A, false, false>(n1, ca, s)) != hipSuccess) return e;
+    ca = col_args(p, c, ws, b, batch);
+    if ((e = launch_col<A, false, false>(n1, ca, s)) != hipSuccess) return e;
+    if ((e = pointwise_cls<A>(p, c, out, out, ws, batch, s)) != hipSuccess) return e;
+    ca = col_args(p, c, out, out, batch);
+    return launch_col<A, true, false>(n1, ca, s);
+  }
+  ColArgs ca = col_args(p, c, out, a, batch);
+  if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
+  ca = col_args(p, c, ws, b, batch);
+  if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
+  RowArgs ra = row_args(p, c, out, out, ws, batch);
+  if ((e = launch_pm<A, true>(n2, ra, s)) != hipSuccess) return e;
+  ca = col_args(p, c, out, out, batch);
+  return launch_col<A, true, true>(n1, ca, s);
+}
+
+template <class A>
+hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
+                          uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s) {
+  MacArgs m;
+  m.dst = out;
+  m.a = a;
+  m.key = key;
+  m.limbs = p->d_limbs;
+  m.cls_limbs = p->d_cls_limbs + p->cls_off[c];
+  m.n_cls = p->cls_cnt[c];
+  m.L = p->L;
+  m.log_n = p->log_n;
+  m.rows = rows;
+  m.cols = cols;
+  m.num_operands = num_operands;
+  m.groups = (num_operands + rows - 1) / rows;
+  m.total = ((uint64_t)m.groups * p->cls_cnt[c]) << p->log_n;
+  const uint64_t want = (m.total + kEltBlock - 1) / kEltBlock;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256ull * 64);
+  hipLaunchKernelGGL((mac_kernel<A>), dim3(blocks), dim3(kEltBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+}  // namespace nttk

@@ -1,0 +1,98 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host-only helpers (admission, root choice) agree with
+the oracle's independent number theory.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+import paper_2410_05934_amd as ntt
+from paper_2410_05934_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(ntt_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ntt.lib()
+    names = _declared_functions()
+    assert "ntt_plan_create" in names and "ntt_forward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_empty_error():
+    lib = ntt.lib()
+    assert b"gfx950" in lib.ntt_version()
+
+
+@pytest.mark.parametrize("N,q,wb,want", [
+    (1024, 536881153, 32, 0),
+    (3, 97, 64, 1),                   # N not a power of two
+    (1 << 17, 786433, 64, 1),         # N too large
+    (1, 97, 64, 1),                   # N too small
+    (1024, 536881153, 16, 1),         # bad word width
+    (1024, 4294967291, 32, 3),        # prime, but 2048 does not divide q-1
+    (1024, 536881155, 32, 2),         # composite
+    (16, (1 << 32) + 97, 32, 4),      # too wide for 32-bit words
+    (16, (1 << 62) + 1, 64, 4),       # too wide for 64-bit words
+    (1024, 4294957057, 32, 0),
+    (1 << 16, 1125899903827969, 64, 0),
+])
+def test_check_modulus_codes(N, q, wb, want):
+    assert ntt.check_modulus(N, q, wb) == want
+
+
+def test_error_message_is_set():
+    lib = ntt.lib()
+    assert lib.ntt_check_modulus(3, 97, 64) == 1
+    assert b"power of two" in lib.ntt_last_error()
+    assert lib.ntt_check_modulus(1024, 536881153, 32) == 0
+    assert lib.ntt_last_error() == b""
+
+
+def test_find_root_matches_oracle_choice():
+    primes = (synth.c2_primes(8) + synth.primes_below(1 << 32, 1 << 11, 4)
+              + synth.primes_below(1 << 62, 1 << 17, 4) + [17, 97, 257, 7681, 12289, 998244353])
+    for q in primes:
+        N = 2
+        while (q - 1) % (2 * N) == 0 and N <= (1 << 16):
+            assert ntt.find_root(N, q) == oracle.psi(N, q), (N, q)
+            N *= 2
+
+
+def test_null_pointer_arguments_are_rejected():
+    lib = ntt.lib()
+    assert lib.ntt_plan_create(None, 1024, None, 1, 32, 0) == 1
+    assert lib.ntt_forward(None, None, 1, None) == 1
+    assert lib.ntt_inverse(None, None, 1, None) == 1
+    assert lib.ntt_polymul(None, None, None, None, 1, None) == 1
+    assert lib.ntt_pointwise_mul(None, None, None, None, 1, None) == 1
+    assert lib.ntt_mac(None, None, None, None, 1, 1, 1, None) == 1
+    assert lib.ntt_plan_destroy(None) == 1
+    out = ctypes.c_uint64()
+    assert lib.ntt_find_root(1024, 97, ctypes.byref(out)) == 3
+
+
+def test_plan_create_rejects_bad_moduli_before_touching_the_device():
+    h = ctypes.c_void_p()
+    lib = ntt.lib()
+    arr = (ctypes.c_uint64 * 2)(536881153, 536881155)
+    assert lib.ntt_plan_create(ctypes.byref(h), 1024, arr, 2, 32, 0) == 2
+    assert h.value is None
+    arr1 = (ctypes.c_uint64 * 1)(536881153)
+    assert lib.ntt_plan_create(ctypes.byref(h), 1024, arr1, 0, 32, 0) == 1
+    assert lib.ntt_plan_create(ctypes.byref(h), 1024, arr1, 1, 32, ntt.flag_split(7)) == 1

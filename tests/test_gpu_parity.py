@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Sizes span several tiles and ragged tails (batch * limbs not a multiple of the
+workgroup's chunk count); full-size cases use the configurations' own shapes.
+Chameleon (arXiv 2410.05934), Sec. II-D / Eq. (1).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_05934_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2410_05934_amd as ntt  # noqa: E402
+from paper_2410_05934_amd.tensors import empty_device, to_device, to_host  # noqa: E402
+
+# Moduli for each arithmetic class, all = 1 mod 2^17 so every N <= 2^16 is admissible.
+Q32 = synth.primes_below(1 << 32, 1 << 17, 2)              # fp64 class, 32-bit words
+Q50 = synth.c2_primes(3)                                   # fp64 class, 64-bit words
+Q60 = synth.primes_below(1 << 61, 1 << 17, 2)              # integer Shoup class
+Q30 = synth.primes_below(1 << 30, 1 << 17, 2)              # small q in 64-bit words
+
+CLASSES = {
+    "u32": (32, Q32),
+    "f64": (64, Q50),
+    "i64": (64, Q60),
+    "small64": (64, Q30),
+    "mixed64": (64, [Q50[0], Q60[0], Q30[0]]),
+}
+
+
+def _data(seed, moduli, batch, N, word_bits):
+    return synth.uniform_poly(seed, moduli, batch, N, np.uint64)
+
+
+def _run_fwd(plan, host, word_bits):
+    d = to_device(host, word_bits)
+    plan.forward(d)
+    torch.cuda.synchronize()
+    return to_host(d, word_bits).astype(np.uint64)
+
+
+def _run_inv(plan, host, word_bits):
+    d = to_device(host, word_bits)
+    plan.inverse(d)
+    torch.cuda.synchronize()
+    return to_host(d, word_bits).astype(np.uint64)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_c1_single_forward_inverse(seed):
+    """N=2^10, one 30-bit prime chosen from the seed, one u32 polynomial."""
+    N = 1 << 10
+    q = synth.c1_prime(seed, N)
+    a = _data(seed, [q], 1, N, 32)
+    plan = ntt.Plan(N, [q], 32)
+    f = _run_fwd(plan, a, 32)
+    assert np.array_equal(f, oracle.forward(a, [q]))
+    assert np.array_equal(_run_inv(plan, f, 32), a)
+    assert np.array_equal(_run_inv(plan, a, 32), oracle.inverse(a, [q]))
+    assert plan.root(0) == oracle.psi(N, q)
+
+
+@pytest.mark.parametrize("cls", list(CLASSES))
+@pytest.mark.parametrize("logn", list(range(1, 17)))
+def test_all_sizes_forward_inverse(cls, logn):
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    batch = 3 if logn >= 12 else 5
+    a = _data(100 + logn, moduli, batch, N, word_bits)
+    plan = ntt.Plan(N, moduli, word_bits)
+    assert np.array_equal(_run_fwd(plan, a, word_bits), oracle.forward(a, moduli))
+    assert np.array_equal(_run_inv(plan, a, word_bits), oracle.inverse(a, moduli))
+
+
+def _valid_splits(logn):
+    out = []
+    for n1 in range(0, logn + 1):
+        if n1 == 0 and 4 <= logn <= 14:
+            out.append(n1)
+        elif n1 == logn and logn <= 5 and n1 != 0:
+            out.append(n1)
+        elif 1 <= n1 <= 5 and 4 <= logn - n1 <= 14:
+            out.append(n1)
+    return out
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+@pytest.mark.parametrize("logn", [5, 10, 13, 14, 15, 16])
+def test_every_split_is_bit_identical(cls, logn):
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    a = _data(7 + logn, moduli, 2, N, word_bits)
+    want_f = oracle.forward(a, moduli)
+    want_i = oracle.inverse(a, moduli)
+    for n1 in _valid_splits(logn):
+        plan = ntt.Plan(N, moduli, word_bits, flags=ntt.flag_split(n1))
+        assert plan.split == n1
+        assert np.array_equal(_run_fwd(plan, a, word_bits), want_f), n1
+        assert np.array_equal(_run_inv(plan, a, word_bits), want_i), n1
+
+
+@pytest.mark.parametrize("logn", [4, 12, 16])
+def test_force_int64_matches_fp64_class(logn):
+    N = 1 << logn
+    a = _data(5, Q50, 2, N, 64)
+    p1 = ntt.Plan(N, Q50, 64)
+    p2 = ntt.Plan(N, Q50, 64, flags=ntt.FLAG_FORCE_INT64)
+    assert p1.limb_class(0) == 1 and p2.limb_class(0) == 2
+    assert np.array_equal(_run_fwd(p1, a, 64), _run_fwd(p2, a, 64))
+    assert np.array_equal(_run_inv(p1, a, 64), _run_inv(p2, a, 64))
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+@pytest.mark.parametrize("logn", [12, 16])
+def test_edge_values(cls, logn):
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    rows = []
+    for q in moduli:
+        rows.append(np.stack([np.zeros(N, np.uint64), np.full(N, q - 1, np.uint64),
+                              np.where(np.arange(N) % 2 == 0, q - 1, 0).astype(np.uint64)]))
+    a = np.ascontiguousarray(np.stack(rows, axis=1))  # [3][L][N]
+    plan = ntt.Plan(N, moduli, word_bits)
+    f = _run_fwd(plan, a, word_bits)
+    assert np.array_equal(f, oracle.forward(a, moduli))
+    assert np.array_equal(_run_inv(plan, f, word_bits), a)
+
+
+@pytest.mark.parametrize("cls", list(CLASSES))
+@pytest.mark.parametrize("logn", [1, 3, 4, 10, 12, 13, 16])
+def test_pointwise_and_polymul(cls, logn):
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    batch = 3
+    a = _data(31, moduli, batch, N, word_bits)
+    b = _data(32, moduli, batch, N, word_bits)
+    plan = ntt.Plan(N, moduli, word_bits)
+    da, db = to_device(a, word_bits), to_device(b, word_bits)
+    out = empty_device(a.shape, word_bits)
+    plan.pointwise_mul(out, da, db)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.pointwise_mul(a, b, moduli))
+    plan.polymul(out, da, db)
+    torch.cuda.synchronize()
+    got = to_host(out, word_bits).astype(np.uint64)
+    assert np.array_equal(got, oracle.polymul(a, b, moduli))
+    # inputs untouched
+    assert np.array_equal(to_host(da, word_bits).astype(np.uint64), a)
+    assert np.array_equal(to_host(db, word_bits).astype(np.uint64), b)
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+def test_polymul_every_split(cls):
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << 14
+    a = _data(41, moduli, 1, N, word_bits)
+    b = _data(42, moduli, 1, N, word_bits)
+    want = oracle.polymul(a, b, moduli)
+    da, db = to_device(a, word_bits), to_device(b, word_bits)
+    for n1 in _valid_splits(14):
+        plan = ntt.Plan(N, moduli, word_bits, flags=ntt.flag_split(n1))
+        out = empty_device(a.shape, word_bits)
+        plan.polymul(out, da, db)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want), n1
+
+
+def test_c2_full_size():
+    """4 polynomials x 36 limbs x 2^16 over the 36 largest primes = 1 mod 2^17 below 2^50."""
+    N, L = 1 << 16, 36
+    moduli = synth.c2_primes(L)
+    a = synth.uniform_poly(0, moduli, 4, N)
+    plan = ntt.Plan(N, moduli, 64)
+    d = to_device(a, 64)
+    plan.forward(d)
+    torch.cuda.synchronize()
+    f = to_host(d, 64)
+    want_f = oracle.forward(a, moduli)
+    assert np.array_equal(f, want_f)
+    # pointwise on the two ciphertext pairs (0,1), (2,3)
+    out = empty_device((2, L, N), 64)
+    plan.pointwise_mul(out, d[0::2].contiguous(), d[1::2].contiguous())
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out, 64), oracle.pointwise_mul(want_f[0::2], want_f[1::2], moduli))
+    plan.inverse(d)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(d, 64), a)
+    # polymul on the pairs, checked on sampled coefficients against the definition
+    da = to_device(np.ascontiguousarray(a[0::2]), 64)
+    db = to_device(np.ascontiguousarray(a[1::2]), 64)
+    plan.polymul(out, da, db)
+    torch.cuda.synchronize()
+    got = to_host(out, 64)
+    want = oracle.polymul(a[0::2], a[1::2], moduli)
+    assert np.array_equal(got, want)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        p, l, k = int(rng.integers(2)), int(rng.integers(L)), int(rng.integers(N))
+        assert int(got[p, l, k]) == oracle.negacyclic_at(a[2 * p, l], a[2 * p + 1, l], moduli[l], k)
+
+
+def test_c3_tfhe_batch_mac():
+    """2048 x 2^10 u32 operands: forward, MAC against a 6x2 key table, inverse (684)."""
+    N, P, rows, cols = 1 << 10, 2048, 6, 2
+    q = synth.c3_prime()
+    a = synth.uniform_poly(3, [q], P, N)
+    key = synth.uniform_poly(4, [q], rows * cols, N).reshape(rows, cols, 1, N)
+    plan = ntt.Plan(N, [q], 32)
+    d = to_device(a, 32)
+    plan.forward(d)
+    k = to_device(key, 32)
+    G = (P + rows - 1) // rows
+    out = empty_device((G, cols, 1, N), 32)
+    plan.mac(out, d, k, rows, cols)
+    torch.cuda.synchronize()
+    fa = oracle.forward(a, [q])
+    assert np.array_equal(to_host(d, 32).astype(np.uint64), fa)
+    want_mac = oracle.mac(fa, key, [q], rows, cols)
+    assert np.array_equal(to_host(out, 32).astype(np.uint64), want_mac)
+    o2 = out.view(G * cols, 1, N)
+    plan.inverse(o2)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(o2, 32).astype(np.uint64),
+                          oracle.inverse(want_mac.reshape(G * cols, 1, N), [q]))
+
+
+def test_repeat_runs_are_identical():
+    N = 1 << 16
+    a = _data(9, Q50, 2, N, 64)
+    plan = ntt.Plan(N, Q50, 64)
+    r1 = _run_fwd(plan, a, 64)
+    r2 = _run_fwd(plan, a, 64)
+    assert np.array_equal(r1, r2)
