@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the negacyclic RNS NTT on one MI355X.
+
+Workload (the CKKS-shaped configuration): 4 polynomials (2 ciphertexts) of
+N = 2^16 in RNS form over the 36 largest primes q = 1 (mod 2^17) below 2^50,
+64-bit words, coefficients uniform in [0, q) (seeded SplitMix64).
+
+One step = the whole hot path over one batch:
+    forward NTT of all 4 polynomials            144 limb transforms
+    pointwise product of the 2 pairs            (72 limb products)
+    inverse NTT of all 4 polynomials            144 limb transforms
+    polymul of the 2 pairs (Eq. (1))            144 forward + 72 inverse
+=> 504 limb transforms per step; `value` = limb transforms per second.
+
+Inputs are resident in HBM before timing starts.  The step rotates over
+`--sets` independent copies of its buffers (151 MB each, 1.2 GB for 8) so that
+no step finds its data in the 256 MB Infinity Cache.  Twiddle tables stay
+resident, as they are meant to.
+
+Also reported: the roofline of the dominant kernel (per-launch HIP events on
+the kernel's own stream, recorded by the library during the timed steps), the
+CPU oracle's throughput on this host, and auxiliary figures (TFHE-shaped batch,
+batched vs one launch per polynomial, single-transform latency).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NTTs/sec and % HBM peak at N=2^16×36 limbs and N=2^10 batch; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2410_05934_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hpp", ".hip", ".cpp")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(name: str, words: int, N: int, limbs: int, word_bytes: int) -> float:
+    """Bytes a launch must move at minimum, by kernel kind.
+
+    row / col pass: every coefficient read once and written once (2 * W per
+    word) -- the pass cannot do less; a row pass also reads one twiddle table
+    of N entries per modulus (8 B per fp64 entry, 16 B per Shoup pair).
+    polymul_row: two operands read, one result written, both tables read.
+    pointwise: two operands read, one result written.
+    """
+    tw = 16 if "_i64_" in name else 8
+    if name.startswith("polymul_row"):
+        return 3.0 * words * word_bytes + 2.0 * limbs * N * tw
+    if name.startswith("row"):
+        return 2.0 * words * word_bytes + 1.0 * limbs * N * tw
+    if name.startswith("col"):
+        return 2.0 * words * word_bytes
+    if name.startswith("pointwise"):
+        return 3.0 * words * word_bytes
+    return 0.0
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    import paper_2410_05934_amd as ntt
+    from paper_2410_05934_amd import synth
+    from paper_2410_05934_amd.tensors import empty_device, to_device
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, L, P = 1 << 16, 36, 4
+    moduli = synth.c2_primes(L)
+    plan = ntt.Plan(N, moduli, 64)
+    _log(f"[bench] plan N={N} L={L} split n1={plan.split}; generating inputs")
+    host = synth.uniform_poly(args.seed, moduli, P, N)
+    X = [to_device(host, 64) for _ in range(args.sets)]
+    PW = [empty_device((2, L, N), 64) for _ in range(args.sets)]
+    C = [empty_device((2, L, N), 64) for _ in range(args.sets)]
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        r = i % args.sets
+        x = X[r]
+        plan.forward(x, stream)
+        plan.pointwise_mul(PW[r], x[0:2], x[2:4], stream)
+        plan.inverse(x, stream)
+        plan.polymul(C[r], x[0:2], x[2:4], stream)
+
+    transforms_per_step = 144 + 144 + 144 + 72
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    _log(f"[bench] warmup done ({args.warmup} steps)")
+
+    # Timed region: K steps bracketed by events on the stream the library
+    # launches on (and a device synchronisation on both sides).
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    ms_per_step = ms / args.steps
+    value = transforms_per_step * args.steps / (ms / 1e3)
+    _log(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.4g} limb-NTT/s (wall {wall:.3f}s)")
+
+    # The same K steps again with the library's per-launch events (two HIP
+    # events on the kernel's own stream around every launch): per-kernel
+    # durations for the breakdown and the roofline.  The events add a little
+    # time between launches, so `value` comes from the run above.
+    ntt.stats_reset()
+    ntt.stats_enable(True)
+    t0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ntt.stats_enable(False)
+    stats = ntt.stats_collect()
+    ms_events = t0.elapsed_time(t1) / args.steps
+    _log(f"[bench] with per-launch events: {ms_events:.4f} ms/step")
+
+    # Dominant kernel and its roofline.
+    breakdown = {}
+    for name, s in stats.items():
+        b = algorithmic_bytes(name, s["words"] // max(1, s["launches"]), N, L, 8)
+        breakdown[name] = {"launches": s["launches"], "avg_us": round(s["avg_ms"] * 1e3, 2),
+                           "share": round(s["total_ms"] / max(1e-9, sum(v["total_ms"] for v in stats.values())), 4),
+                           "alg_GBps": round(b / (s["avg_ms"] * 1e-3) / 1e9, 1) if b else None}
+    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    d = stats[dom]
+    alg = algorithmic_bytes(dom, d["words"] // d["launches"], N, L, 8)
+    achieved = alg / (d["avg_ms"] * 1e-3) / 1e9
+    traffic = load_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": alg,
+                "avg_launch_us": round(d["avg_ms"] * 1e3, 2)}
+
+    extra = {"breakdown": breakdown, "ms_per_step_with_launch_events": round(ms_events, 4),
+             "rotating_sets": args.sets}
+    if not args.no_aux:
+        extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
+    return value, ms_per_step, roofline, extra
+
+
+def _time(torch, fn, reps, stream):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, stream):
+    out = {}
+    # C2 batched (one call over 4 polynomials) vs plain (one call per RNS polynomial).
+    t_b = _time(torch, lambda: plan2.forward(x2, stream), 20, stream)
+    t_p = _time(torch, lambda: [plan2.forward(x2[i:i + 1], stream) for i in range(4)], 20, stream)
+    out["c2_forward"] = {"batched_us": round(t_b * 1e3, 2), "per_poly_launch_us": round(t_p * 1e3, 2),
+                         "batched_limb_ntt_per_s": 144 / (t_b * 1e-3), "batched_over_plain": round(t_p / t_b, 3)}
+    # C3 TFHE-shaped: 2048 x 2^10 u32 forward, MAC (6 rows x 2 cols), 684 inverse.
+    N, Pn, rows, cols = 1 << 10, 2048, 6, 2
+    q = synth.c3_prime()
+    p3 = ntt.Plan(N, [q], 32)
+    a = to_device(synth.uniform_poly(5, [q], Pn, N), 32)
+    key = to_device(synth.uniform_poly(6, [q], rows * cols, N), 32)
+    G = (Pn + rows - 1) // rows
+    acc = empty_device((G * cols, 1, N), 32)
+    work = a.clone()
+
+    def c3_batched():
+        work.copy_(a)
+        p3.forward(work, stream)
+        p3.mac(acc, work, key, rows, cols, stream)
+        p3.inverse(acc, stream)
+
+    def c3_plain():
+        work.copy_(a)
+        for i in range(Pn):
+            p3.forward(work[i:i + 1], stream)
+        p3.mac(acc, work, key, rows, cols, stream)
+        for i in range(G * cols):
+            p3.inverse(acc[i:i + 1], stream)
+
+    tb = _time(torch, c3_batched, 20, stream)
+    tp = _time(torch, c3_plain, 3, stream)
+    copy_ms = _time(torch, lambda: work.copy_(a), 20, stream)
+    n3 = Pn + G * cols
+    out["c3_tfhe"] = {"batched_us": round(tb * 1e3, 2), "plain_us": round(tp * 1e3, 2),
+                      "input_copy_us": round(copy_ms * 1e3, 2),
+                      "batched_ntt_per_s": n3 / ((tb - copy_ms) * 1e-3),
+                      "batched_over_plain": round(tp / tb, 2)}
+    # C1 latency: one 2^10 forward + inverse, u32.
+    q1 = synth.c1_prime(0)
+    p1 = ntt.Plan(N, [q1], 32)
+    x1 = to_device(synth.uniform_poly(7, [q1], 1, N), 32)
+    t1 = _time(torch, lambda: (p1.forward(x1, stream), p1.inverse(x1, stream)), 200, stream)
+    out["c1_fwd_inv_us"] = round(t1 * 1e3, 2)
+    return out
+
+
+def run_cpu_baseline(args):
+    """The oracle (plain radix-2, unsigned __int128 %, one thread per core)
+    timed on a bounded sample: whole C2 steps repeated until cpu_seconds pass."""
+    import oracle
+    from paper_2410_05934_amd import synth
+    N, L = 1 << 16, 36
+    moduli = synth.c2_primes(L)
+    x = synth.uniform_poly(args.seed, moduli, 4, N)
+    cores = oracle.num_cores()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        f = oracle.forward(x, moduli, cores)
+        oracle.pointwise_mul(f[0:2], f[2:4], moduli)
+        oracle.inverse(f, moduli, cores)
+        oracle.polymul(x[0:2], x[2:4], moduli, cores)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= args.cpu_seconds:
+            break
+    return {"value": 504 * steps / el, "unit": "limb-NTT/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} whole steps of the same workload (4x36x2^16, fwd+pointwise+inv+polymul), "
+                      f"{el:.1f} s, {cores} threads over (poly, limb) rows"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--sets", type=int, default=8, help="rotating buffer sets (defeats the 256 MB MALL)")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-aux", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(every (poly, limb) transform is independent; see the sharding notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    value, ms_per_step, roofline, extra = run_gpu(args)
+    cpu = None if args.no_cpu else run_cpu_baseline(args)
+    line = {
+        "metric": METRIC, "value": value, "unit": "limb-NTT/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "ckks-rns: 4 polys x 36 limbs x N=2^16, 36 largest primes q=1 mod 2^17 "
+                               "below 2^50, u64 words; step = fwd + pointwise + inv + polymul",
+                   "N": 1 << 16, "limbs": 36, "polys": 4, "word_bits": 64,
+                   "transforms_per_step": 504, "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -22,8 +22,9 @@
  * Ownership: the caller owns every data buffer (device memory, e.g. from a
  * PyTorch tensor).  A plan owns its device twiddle tables and is read-only
  * after creation, so one plan may be used from several host threads and
- * streams at once (polymul at N > 2^12 draws on the plan's own workspace and
- * serialises itself per plan).  All transform calls are asynchronous on the
+ * streams at once (a polymul with a column pass takes a stream-ordered
+ * workspace with hipMallocAsync on the caller's stream and releases it there
+ * with hipFreeAsync).  All transform calls are asynchronous on the
  * given stream (a hipStream_t passed as void*, NULL = the default stream);
  * their results are valid once the stream has reached that point.
  *
@@ -117,6 +118,23 @@ ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, u
  * out must not alias a or b. */
 ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,
                        void* stream);
+
+/* Per-kernel timing of this library's own launches (tracing).  While enabled,
+ * every kernel launch is bracketed by two HIP events recorded on the stream the
+ * kernel is launched on.  ntt_stats_collect() waits for the recorded events and
+ * fills out[0 .. min(cap, count)-1] with one entry per kernel name (sorted by
+ * name); *count receives the number of names.  Aggregates persist until
+ * ntt_stats_reset().  Enabling adds two event records per launch. */
+typedef struct {
+  char name[64];      /* e.g. "row_fwd_f64l_log12_2pass" */
+  uint64_t launches;  /* launches recorded */
+  uint64_t words;     /* coefficient words covered, summed over launches */
+  double total_ms;    /* summed device time between each launch's two events */
+} ntt_kernel_stat;
+
+ntt_status ntt_stats_enable(int on);
+ntt_status ntt_stats_reset(void);
+ntt_status ntt_stats_collect(ntt_kernel_stat* out, uint32_t cap, uint32_t* count);
 
 /* Host-only helpers (no device needed). */
 

@@ -16,7 +16,7 @@ import os
 import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
-           "FLAG_FORCE_INT64", "flag_split"]
+           "FLAG_FORCE_INT64", "flag_split", "stats_enable", "stats_reset", "stats_collect"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libntt.so")
@@ -61,7 +61,39 @@ _SIGS = {
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
+    "ntt_stats_enable": [ctypes.c_int],
+    "ntt_stats_reset": [],
+    "ntt_stats_collect": [_vp, _u32, ctypes.POINTER(_u32)],
 }
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_uint64),
+                ("words", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+def stats_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events on its own stream."""
+    _check(lib().ntt_stats_enable(1 if on else 0), "ntt_stats_enable")
+
+
+def stats_reset() -> None:
+    _check(lib().ntt_stats_reset(), "ntt_stats_reset")
+
+
+def stats_collect() -> dict:
+    """{kernel name: {"launches", "words", "total_ms", "avg_ms"}} since the last reset."""
+    n = _u32()
+    _check(lib().ntt_stats_collect(None, 0, ctypes.byref(n)), "ntt_stats_collect")
+    arr = (KernelStat * max(1, n.value))()
+    _check(lib().ntt_stats_collect(ctypes.cast(arr, _vp), n.value, ctypes.byref(n)), "ntt_stats_collect")
+    out = {}
+    for i in range(n.value):
+        s = arr[i]
+        out[s.name.decode()] = {"launches": int(s.launches), "words": int(s.words),
+                                "total_ms": float(s.total_ms),
+                                "avg_ms": float(s.total_ms) / max(1, int(s.launches))}
+    return out
 
 
 def lib():

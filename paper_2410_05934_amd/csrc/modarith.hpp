@@ -154,6 +154,7 @@ struct ArF64S {
   using V = double;
   using TW = double;
   static constexpr int kCls = 0;
+  static constexpr const char* kName = "f64s";
   static constexpr bool kCenterRounds = false;
   double q, qinv;
   NTT_HD explicit ArF64S(const LimbDev& d) : q(d.qd), qinv(d.qinv) {}
@@ -190,6 +191,7 @@ struct ArF64L {
   using V = double;
   using TW = double;
   static constexpr int kCls = 1;
+  static constexpr const char* kName = "f64l";
   static constexpr bool kCenterRounds = true;
   double q, qinv;
   NTT_HD explicit ArF64L(const LimbDev& d) : q(d.qd), qinv(d.qinv) {}
@@ -230,6 +232,7 @@ struct ArI64 {
   using V = uint64_t;
   using TW = TwI64;
   static constexpr int kCls = 2;
+  static constexpr const char* kName = "i64";
   static constexpr bool kCenterRounds = false;
   uint64_t q, q2, mu;
   uint32_t qbits;

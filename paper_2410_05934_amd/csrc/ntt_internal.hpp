@@ -26,8 +26,32 @@ struct ntt_plan_s {
 
 namespace nttk {
 
+// Column stages used by polymul.  The fused row kernel holds two operands in
+// registers; at 2^14-word rows (1024 threads, at most 128 VGPRs) it would
+// spill, so such plans multiply with a 2^13-word row pass instead.
+inline uint32_t polymul_split(const ntt_plan_s* p) {
+  return (p->log_n1 == 0 && p->log_n == 14) ? 1u : p->log_n1;
+}
+
 ntt_status fail(ntt_status st, const char* fmt, ...);
 ntt_status hip_fail(hipError_t e, const char* what);
+
+// Per-launch timing (enabled through ntt_stats_enable).  When enabled, the
+// launch is bracketed by two events on its own stream.
+bool stats_enabled();
+class LaunchTimer {
+ public:
+  LaunchTimer(const char* kind, const char* cls, int size_log, bool inv, bool two_pass,
+              uint64_t words, hipStream_t s);
+  ~LaunchTimer();
+  LaunchTimer(const LaunchTimer&) = delete;
+  LaunchTimer& operator=(const LaunchTimer&) = delete;
+
+ private:
+  bool on_ = false;
+  int slot_ = -1;
+  hipStream_t s_ = nullptr;
+};
 
 // Split chosen by the tuning cache for this shape, or `fallback`.
 uint32_t tuned_split(uint32_t N, uint32_t L, uint32_t word_bits, uint32_t fallback);

@@ -105,25 +105,51 @@ struct RowShape {
   static constexpr int nst(int j) { return j < K - 1 ? 4 : LAST; }
 };
 
+#define NTT_GLOBAL __attribute__((address_space(1)))
+
+// Tables live in device global memory; saying so lets the compiler use global
+// (not flat) loads for pointers that come out of the limb constants.
+template <class T>
+__device__ __forceinline__ const NTT_GLOBAL T* gptr(const T* p) {
+  return (const NTT_GLOBAL T*)p;
+}
+
 __device__ __forceinline__ uint32_t ins_bits(uint32_t tt, uint32_t u, int hb) {
   return ((tt >> hb) << (hb + 4)) | (u << hb) | (tt & ((1u << hb) - 1u));
 }
 __device__ __forceinline__ uint32_t lds_pad(uint32_t y) { return y + (y >> 4); }
 
+// One table entry from global memory (fp64 entry or Shoup pair).
+template <class TW>
+__device__ __forceinline__ TW load1(const NTT_GLOBAL TW* p) {
+  if constexpr (sizeof(TW) == 16) {
+    typedef uint64_t uvec2 __attribute__((ext_vector_type(2)));
+    const uvec2 t = *reinterpret_cast<const NTT_GLOBAL uvec2*>(p);
+    TW w;
+    w.w = t.x;
+    w.ws = t.y;
+    return w;
+  } else {
+    return *p;
+  }
+}
+
 // Load G consecutive twiddles starting at an index that is a multiple of G.
 template <class TW, int G>
-__device__ __forceinline__ void load_tw(TW (&w)[G], const TW* __restrict__ tab, uint32_t idx) {
+__device__ __forceinline__ void load_tw(TW (&w)[G], const TW* __restrict__ tab_in, uint32_t idx) {
+  const NTT_GLOBAL TW* tab = gptr(tab_in);
   if constexpr (sizeof(TW) == 8 && G >= 2) {
-    const double2* p = reinterpret_cast<const double2*>(tab + idx);
+    typedef double dvec2 __attribute__((ext_vector_type(2)));
+    const NTT_GLOBAL dvec2* p = reinterpret_cast<const NTT_GLOBAL dvec2*>(tab + idx);
 #pragma unroll
     for (int i = 0; i < G / 2; ++i) {
-      const double2 t = p[i];
+      const dvec2 t = p[i];
       w[2 * i] = t.x;
       w[2 * i + 1] = t.y;
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < G; ++i) w[i] = tab[idx + i];
+    for (int i = 0; i < G; ++i) w[i] = load1<TW>(tab + idx + i);
   }
 }
 
@@ -309,18 +335,45 @@ row_kernel(RowArgs args) {
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twf);
     row_forward_from<A, LOGN2, 0>(ar, v, tw, cp.base, tt, lds);
-    constexpr int HL = S::hb(S::K - 1);
-    if (cp.valid) {
+    if constexpr (S::K > 1) {
+      // The last round holds 16 consecutive words per thread; re-deal them
+      // through LDS so that each store instruction writes contiguous words.
 #pragma unroll
-      for (int u = 0; u < 16; ++u) dst[ins_bits(tt, u, HL)] = ar.to_word(v[u]);
+      for (int u = 0; u < 16; ++u) lds[lds_pad((tt << 4) | u)] = v[u];
+      __syncthreads();
+      if (cp.valid) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const uint32_t y = tt + u * S::TPC;
+          dst[y] = ar.to_word(lds[lds_pad(y)]);
+        }
+      }
+    } else if (cp.valid) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) dst[u] = ar.to_word(v[u]);
     }
   } else {
-    constexpr int HL = S::hb(S::K - 1);
+    if constexpr (S::K > 1) {
+      // Contiguous loads into LDS, then each thread takes 16 consecutive words.
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const W x = cp.valid ? src[ins_bits(tt, u, HL)] : W(0);
-      v[u] = ar.from_word(x);
-      ar.center(v[u]);
+      for (int u = 0; u < 16; ++u) {
+        const uint32_t y = tt + u * S::TPC;
+        const W x = cp.valid ? src[y] : W(0);
+        V t = ar.from_word(x);
+        ar.center(t);
+        lds[lds_pad(y)] = t;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = lds[lds_pad((tt << 4) | u)];
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const W x = cp.valid ? src[u] : W(0);
+        v[u] = ar.from_word(x);
+        ar.center(v[u]);
+      }
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twi);
     row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, v, tw, cp.base, tt, lds, ld);
@@ -409,7 +462,7 @@ col_kernel(ColArgs args) {
   W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + off;
   V v[N1];
   if constexpr (!INV) {
-    const TW* __restrict__ tw = reinterpret_cast<const TW*>(ld.twf);
+    const NTT_GLOBAL TW* tw = gptr(reinterpret_cast<const TW*>(ld.twf));
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       const W x = valid ? src[(uint64_t)k << args.log_n2] : W(0);
@@ -420,7 +473,7 @@ col_kernel(ColArgs args) {
       const int t = N1 >> (s + 1);
 #pragma unroll
       for (int i = 0; i < (1 << s); ++i) {
-        const TW w = tw[(1 << s) + i];
+        const TW w = load1<TW>(tw + (1 << s) + i);
 #pragma unroll
         for (int j = 0; j < t; ++j) ar.ct(v[2 * i * t + j], v[2 * i * t + j + t], w);
       }
@@ -437,7 +490,7 @@ col_kernel(ColArgs args) {
         dst[(uint64_t)k << args.log_n2] = TWO_PASS ? ar.to_raw(v[k]) : ar.to_word(v[k]);
     }
   } else {
-    const TW* __restrict__ tw = reinterpret_cast<const TW*>(ld.twi);
+    const NTT_GLOBAL TW* tw = gptr(reinterpret_cast<const TW*>(ld.twi));
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       const W x = valid ? src[(uint64_t)k << args.log_n2] : W(0);
@@ -454,7 +507,7 @@ col_kernel(ColArgs args) {
       } else {
 #pragma unroll
         for (int i = 0; i < (1 << s); ++i) {
-          const TW w = tw[(1 << s) + i];
+          const TW w = load1<TW>(tw + (1 << s) + i);
 #pragma unroll
           for (int j = 0; j < t; ++j) ar.gs(v[2 * i * t + j], v[2 * i * t + j + t], w);
         }

@@ -17,6 +17,7 @@ template <class A, int LOGN2, bool INV, bool TWO>
 hipError_t launch_row_n(const RowArgs& a, hipStream_t s) {
   using S = RowShape<LOGN2>;
   const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
+  LaunchTimer t("row", A::kName, LOGN2, INV, TWO, (uint64_t)a.total_chunks << LOGN2, s);
   hipLaunchKernelGGL((row_kernel<A, LOGN2, INV, TWO>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
   return hipGetLastError();
 }
@@ -25,6 +26,7 @@ template <class A, int LOGN2, bool TWO>
 hipError_t launch_pm_n(const RowArgs& a, hipStream_t s) {
   using S = RowShape<LOGN2>;
   const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
+  LaunchTimer t("polymul_row", A::kName, LOGN2, false, TWO, (uint64_t)a.total_chunks << LOGN2, s);
   hipLaunchKernelGGL((polymul_row_kernel<A, LOGN2, TWO>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
   return hipGetLastError();
 }
@@ -32,6 +34,7 @@ hipError_t launch_pm_n(const RowArgs& a, hipStream_t s) {
 template <class A, int LOGN1, bool INV, bool TWO>
 hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
   const uint32_t blocks = (a.total_cols + kColBlock - 1) / kColBlock;
+  LaunchTimer t("col", A::kName, LOGN1, INV, TWO, (uint64_t)a.total_cols << LOGN1, s);
   hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(kColBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -67,7 +70,6 @@ hipError_t launch_pm(int logn2, const RowArgs& a, hipStream_t s) {
     case 11: return launch_pm_n<A, 11, TWO>(a, s);
     case 12: return launch_pm_n<A, 12, TWO>(a, s);
     case 13: return launch_pm_n<A, 13, TWO>(a, s);
-    case 14: return launch_pm_n<A, 14, TWO>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -85,7 +87,8 @@ hipError_t launch_col(int logn1, const ColArgs& a, hipStream_t s) {
 }
 
 inline RowArgs row_args(const ntt_plan_s* p, int c, void* dst, const void* src, const void* src2,
-                        uint32_t batch) {
+                        uint32_t batch, int n1 = -1) {
+  if (n1 < 0) n1 = (int)p->log_n1;
   RowArgs a;
   a.dst = dst;
   a.src = src;
@@ -95,12 +98,14 @@ inline RowArgs row_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.n_cls = p->cls_cnt[c];
   a.L = p->L;
   a.log_n = p->log_n;
-  a.log_n1 = p->log_n1;
-  a.total_chunks = batch * p->cls_cnt[c] << p->log_n1;
+  a.log_n1 = (uint32_t)n1;
+  a.total_chunks = batch * p->cls_cnt[c] << n1;
   return a;
 }
 
-inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, uint32_t batch) {
+inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, uint32_t batch,
+                        int n1 = -1) {
+  if (n1 < 0) n1 = (int)p->log_n1;
   ColArgs a;
   a.dst = dst;
   a.src = src;
@@ -109,7 +114,7 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.n_cls = p->cls_cnt[c];
   a.L = p->L;
   a.log_n = p->log_n;
-  a.log_n2 = p->log_n - p->log_n1;
+  a.log_n2 = p->log_n - (uint32_t)n1;
   a.total_cols = (batch * p->cls_cnt[c]) << a.log_n2;
   return a;
 }
@@ -158,6 +163,7 @@ hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a,
   ea.total = ((uint64_t)batch * p->cls_cnt[c]) << p->log_n;
   const uint64_t want = (ea.total + kEltBlock - 1) / kEltBlock;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256ull * 64);
+  LaunchTimer t("pointwise", A::kName, p->log_n, false, false, ea.total, s);
   hipLaunchKernelGGL((pointwise_kernel<A>), dim3(blocks), dim3(kEltBlock), 0, s, ea);
   return hipGetLastError();
 }
@@ -165,29 +171,29 @@ hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a,
 template <class A>
 hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
                               void* ws, uint32_t batch, hipStream_t s) {
-  const int n = p->log_n, n1 = p->log_n1, n2 = n - n1;
+  const int n = p->log_n, n1 = (int)polymul_split(p), n2 = n - n1;
   hipError_t e;
   if (n1 == 0) {
-    RowArgs ra = row_args(p, c, out, a, b, batch);
+    RowArgs ra = row_args(p, c, out, a, b, batch, n1);
     return launch_pm<A, false>(n2, ra, s);
   }
   if (n2 == 0) {
     // Tiny N: forward both into out / ws, multiply, inverse.
-    ColArgs ca = col_args(p, c, out, a, batch);
+    ColArgs ca = col_args(p, c, out, a, batch, n1);
     if ((e = launch_col<A, false, false>(n1, ca, s)) != hipSuccess) return e;
-    ca = col_args(p, c, ws, b, batch);
+    ca = col_args(p, c, ws, b, batch, n1);
     if ((e = launch_col<A, false, false>(n1, ca, s)) != hipSuccess) return e;
     if ((e = pointwise_cls<A>(p, c, out, out, ws, batch, s)) != hipSuccess) return e;
-    ca = col_args(p, c, out, out, batch);
+    ca = col_args(p, c, out, out, batch, n1);
     return launch_col<A, true, false>(n1, ca, s);
   }
-  ColArgs ca = col_args(p, c, out, a, batch);
+  ColArgs ca = col_args(p, c, out, a, batch, n1);
   if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
-  ca = col_args(p, c, ws, b, batch);
+  ca = col_args(p, c, ws, b, batch, n1);
   if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
-  RowArgs ra = row_args(p, c, out, out, ws, batch);
+  RowArgs ra = row_args(p, c, out, out, ws, batch, n1);
   if ((e = launch_pm<A, true>(n2, ra, s)) != hipSuccess) return e;
-  ca = col_args(p, c, out, out, batch);
+  ca = col_args(p, c, out, out, batch, n1);
   return launch_col<A, true, true>(n1, ca, s);
 }
 
@@ -210,6 +216,7 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
   m.total = ((uint64_t)m.groups * p->cls_cnt[c]) << p->log_n;
   const uint64_t want = (m.total + kEltBlock - 1) / kEltBlock;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256ull * 64);
+  LaunchTimer t("mac", A::kName, p->log_n, false, false, m.total, s);
   hipLaunchKernelGGL((mac_kernel<A>), dim3(blocks), dim3(kEltBlock), 0, s, m);
   return hipGetLastError();
 }

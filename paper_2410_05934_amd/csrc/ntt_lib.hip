@@ -447,7 +447,7 @@ ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b,
   if (out == a || out == b) return fail(NTT_EINVAL, "out must not alias a or b");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = nullptr;
-  const bool need_ws = plan->log_n1 != 0;
+  const bool need_ws = polymul_split(plan) != 0;
   if (need_ws) {
     const size_t bytes = ((size_t)batch * plan->L << plan->log_n) * (plan->word_bits / 8);
     hipError_t e = hipMallocAsync(&ws, bytes, s);
