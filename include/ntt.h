@@ -59,7 +59,9 @@ typedef enum {
 /* Plan flags.  NTT_FLAG_SPLIT(n1) forces the pass split N = 2^n1 * 2^(log2 N - n1):
  * n1 = 0 is a single on-chip pass (N <= 2^14), n1 >= 1 a column pass of n1
  * stages followed by a row pass (the row part must be 2^4 .. 2^14 words, or
- * n1 = log2 N for N < 16).  Without it the plan takes the tuned/default split. */
+ * n1 = log2 N for N < 16).  Without it each call takes the split the tuning
+ * table records for its shape (see ntt_tune_split), else the default:
+ * N < 16 one column pass, N <= 2^12 one row pass, else 2^12-word rows. */
 #define NTT_FLAG_SPLIT(n1) ((uint32_t)(((n1) + 1) & 0x1f) << 8)
 #define NTT_FLAG_SPLIT_MASK (0x1fu << 8)
 /* Force the 64-bit integer (Shoup) arithmetic for every limb, even where the
@@ -87,6 +89,9 @@ ntt_status ntt_plan_root(ntt_plan_t plan, uint32_t limb, uint64_t* psi);
 
 /* The pass split in use: *log_n1 = number of column stages (0 = single pass). */
 ntt_status ntt_plan_split(ntt_plan_t plan, uint32_t* log_n1);
+
+/* The split a call over `batch` polynomials would use (tuning table or default). */
+ntt_status ntt_plan_split_for(ntt_plan_t plan, uint32_t batch, uint32_t* log_n1);
 
 /* Arithmetic class of a limb: 0 = exact fp64 for 32-bit words, 1 = exact fp64
  * for q < 2^50 - 2^10 in 64-bit words, 2 = 64-bit integer Shoup. */
@@ -118,6 +123,70 @@ ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, u
  * out must not alias a or b. */
 ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,
                        void* stream);
+
+/* ---- Ragged batches in one persistent launch ---------------------------- */
+
+/* One job of a ragged batch: an in-place forward or inverse transform of
+ * data[batch][L][N] under `plan` (any N >= 16, any limb count and moduli). */
+#define NTT_OP_FORWARD 0u
+#define NTT_OP_INVERSE 1u
+typedef struct {
+  ntt_plan_t plan;
+  uint32_t op;     /* NTT_OP_FORWARD or NTT_OP_INVERSE */
+  uint32_t batch;  /* polynomials in data */
+  void* data;      /* device words, [batch][L][N] of the plan's width */
+} ntt_job;
+
+typedef struct ntt_ragged_s* ntt_ragged_t;
+
+/* ntt_ragged_create flags. */
+#define NTT_RAGGED_NO_GRAPH (1u << 0)           /* launch directly instead of replaying a hipGraph */
+#define NTT_RAGGED_ROW_LOG(n2) (((uint32_t)(n2) & 0xfu) << 8) /* force row length 2^n2 (11 or 12) for N >= 2^13 */
+
+/* Build a reusable ragged batch over jobs[0 .. n-1] (the paper's single kernel
+ * launch for the hybrid NTT, Sec. V-D, applied to a mixed batch).  The work list
+ * -- one limb-row per item, or up to 16 rows of one small N -- is built on the
+ * host, sorted largest first and uploaded once.  The plans and data buffers
+ * named by the jobs must stay valid for the life of the handle.  Jobs of 32-bit
+ * and 64-bit words run as one persistent launch per width. */
+ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n, uint32_t flags);
+
+/* Run the batch on `stream`: reset the work counter and launch the persistent
+ * kernel(s).  Unless NTT_RAGGED_NO_GRAPH was given, the first run captures these
+ * launches into a hipGraph and every run replays it.  Runs of one handle must
+ * not overlap in time (they share the work counter). */
+ntt_status ntt_ragged_run(ntt_ragged_t r, void* stream);
+
+/* Work items and persistent workgroups of a batch. */
+ntt_status ntt_ragged_info(ntt_ragged_t r, uint32_t* items, uint32_t* workgroups);
+
+ntt_status ntt_ragged_destroy(ntt_ragged_t r);
+
+/* One-shot form: create, run without a graph, wait for `stream`, destroy. */
+ntt_status ntt_batch_ragged(const ntt_job* jobs, uint32_t n, void* stream);
+
+/* ---- Autotuner ------------------------------------------------------------ */
+
+/* Time every admissible pass split for (N, moduli, word_bits) on `batch`
+ * polynomials of scratch data (forward + inverse, HIP events on an internal
+ * stream), record the fastest in the library's tuning table and return it.
+ * Later calls with a similar number of limb-rows (same power-of-two bucket of
+ * batch * L) and no forced split use it.  The paper's switch trigger (chunks
+ * closest to the SM count, Sec. V-D) is for one polynomial; a batch changes the
+ * concurrency, so the split is measured per (N, class, rows). */
+ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_moduli,
+                          uint32_t word_bits, uint32_t batch, uint32_t* best_n1, float* best_us);
+
+/* Time row lengths 2^11 and 2^12 for the in-workgroup split of ragged batches
+ * with this N (>= 2^13) and record the faster; returns log2 of the row length. */
+ntt_status ntt_tune_ragged(uint32_t N, const uint64_t* moduli, uint32_t num_moduli,
+                           uint32_t batch, uint32_t* best_row_log, float* best_us);
+
+/* Save / load / clear the tuning table (a small JSON file).  At first use the
+ * library loads the file named by the environment variable NTT_TUNE_FILE, if set. */
+ntt_status ntt_tune_save(const char* path);
+ntt_status ntt_tune_load(const char* path);
+ntt_status ntt_tune_clear(void);
 
 /* Per-kernel timing of this library's own launches (tracing).  While enabled,
  * every kernel launch is bracketed by two HIP events recorded on the stream the

@@ -16,7 +16,9 @@ import os
 import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
-           "FLAG_FORCE_INT64", "flag_split", "stats_enable", "stats_reset", "stats_collect"]
+           "FLAG_FORCE_INT64", "flag_split", "stats_enable", "stats_reset", "stats_collect",
+           "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH",
+           "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libntt.so")
@@ -61,10 +63,111 @@ _SIGS = {
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
+    "ntt_plan_split_for": [_vp, _u32, ctypes.POINTER(_u32)],
+    "ntt_ragged_create": [ctypes.POINTER(_vp), _vp, _u32, _u32],
+    "ntt_ragged_run": [_vp, _vp],
+    "ntt_ragged_info": [_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u32)],
+    "ntt_ragged_destroy": [_vp],
+    "ntt_batch_ragged": [_vp, _u32, _vp],
+    "ntt_tune_split": [_u32, ctypes.POINTER(_u64), _u32, _u32, _u32, ctypes.POINTER(_u32),
+                       ctypes.POINTER(ctypes.c_float)],
+    "ntt_tune_ragged": [_u32, ctypes.POINTER(_u64), _u32, _u32, ctypes.POINTER(_u32),
+                        ctypes.POINTER(ctypes.c_float)],
+    "ntt_tune_save": [ctypes.c_char_p],
+    "ntt_tune_load": [ctypes.c_char_p],
+    "ntt_tune_clear": [],
     "ntt_stats_enable": [ctypes.c_int],
     "ntt_stats_reset": [],
     "ntt_stats_collect": [_vp, _u32, ctypes.POINTER(_u32)],
 }
+
+
+OP_FORWARD = 0
+OP_INVERSE = 1
+RAGGED_NO_GRAPH = 1
+
+
+def ragged_row_log(n2: int) -> int:
+    """NTT_RAGGED_ROW_LOG(n2) flag."""
+    return (n2 & 0xF) << 8
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("plan", _vp), ("op", _u32), ("batch", _u32), ("data", _vp)]
+
+
+class RaggedBatch:
+    """A reusable ragged batch: jobs (plan, op, tensor) run as one persistent
+    launch per word width, replayed from a hipGraph unless no_graph is set.
+    The plans and tensors must outlive the batch."""
+
+    def __init__(self, jobs, flags: int = 0):
+        self._keep = list(jobs)
+        arr = (_Job * len(jobs))()
+        for i, (plan, op, t) in enumerate(jobs):
+            b = plan._batch_of(t, f"job {i}")
+            arr[i] = _Job(plan._h.value, int(op), b, t.data_ptr())
+        h = _vp()
+        _check(lib().ntt_ragged_create(ctypes.byref(h), ctypes.cast(arr, _vp), len(jobs), flags),
+               "ntt_ragged_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().ntt_ragged_run(self._h, _stream_handle(stream)), "ntt_ragged_run")
+
+    def info(self):
+        items, wgs = _u32(), _u32()
+        _check(lib().ntt_ragged_info(self._h, ctypes.byref(items), ctypes.byref(wgs)), "ntt_ragged_info")
+        return int(items.value), int(wgs.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ntt_ragged_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_ragged(jobs, stream=None) -> None:
+    """One-shot ragged batch (no graph); returns after the stream has finished it."""
+    arr = (_Job * len(jobs))()
+    for i, (plan, op, t) in enumerate(jobs):
+        arr[i] = _Job(plan._h.value, int(op), plan._batch_of(t, f"job {i}"), t.data_ptr())
+    _check(lib().ntt_batch_ragged(ctypes.cast(arr, _vp), len(jobs), _stream_handle(stream)),
+           "ntt_batch_ragged")
+
+
+def tune_split(N: int, moduli, word_bits: int, batch: int):
+    """Autotune the pass split for this shape; returns (best n1, microseconds per fwd+inv)."""
+    arr = (_u64 * len(moduli))(*[int(q) for q in moduli])
+    best, us = _u32(), ctypes.c_float()
+    _check(lib().ntt_tune_split(N, arr, len(moduli), word_bits, batch, ctypes.byref(best),
+                                ctypes.byref(us)), "ntt_tune_split")
+    return int(best.value), float(us.value)
+
+
+def tune_ragged(N: int, moduli, batch: int):
+    arr = (_u64 * len(moduli))(*[int(q) for q in moduli])
+    best, us = _u32(), ctypes.c_float()
+    _check(lib().ntt_tune_ragged(N, arr, len(moduli), batch, ctypes.byref(best), ctypes.byref(us)),
+           "ntt_tune_ragged")
+    return int(best.value), float(us.value)
+
+
+def tune_save(path: str) -> None:
+    _check(lib().ntt_tune_save(path.encode()), "ntt_tune_save")
+
+
+def tune_load(path: str) -> None:
+    _check(lib().ntt_tune_load(path.encode()), "ntt_tune_load")
+
+
+def tune_clear() -> None:
+    _check(lib().ntt_tune_clear(), "ntt_tune_clear")
 
 
 class KernelStat(ctypes.Structure):
@@ -175,6 +278,11 @@ class Plan:
     def limb_class(self, limb: int) -> int:
         out = _u32()
         _check(lib().ntt_plan_limb_class(self._h, limb, ctypes.byref(out)), "ntt_plan_limb_class")
+        return int(out.value)
+
+    def split_for(self, batch: int) -> int:
+        out = _u32()
+        _check(lib().ntt_plan_split_for(self._h, batch, ctypes.byref(out)), "ntt_plan_split_for")
         return int(out.value)
 
     @property

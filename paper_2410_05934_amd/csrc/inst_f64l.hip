@@ -3,11 +3,11 @@
 
 namespace nttk {
 template hipError_t transform_cls<ArF64L>(const ntt_plan_s*, int, void*, uint32_t, bool,
-                                         hipStream_t);
+                                         uint32_t, hipStream_t);
 template hipError_t pointwise_cls<ArF64L>(const ntt_plan_s*, int, void*, const void*, const void*,
                                          uint32_t, hipStream_t);
 template hipError_t polymul_cls<ArF64L>(const ntt_plan_s*, int, void*, const void*, const void*,
-                                       void*, uint32_t, hipStream_t);
+                                       void*, uint32_t, uint32_t, hipStream_t);
 template hipError_t mac_cls<ArF64L>(const ntt_plan_s*, int, void*, const void*, const void*,
                                    uint32_t, uint32_t, uint32_t, hipStream_t);
 }  // namespace nttk

@@ -11,14 +11,32 @@
 #include "../../include/ntt.h"
 #include "modarith.hpp"
 
+namespace nttk {
+// A device-resident twiddle table pair (forward, inverse) for one prime and
+// arithmetic class, of length 2^log_len; shared by reference count.
+struct PrimeTable {
+  int device = 0;
+  uint64_t q = 0;
+  uint32_t cls = 0;
+  uint32_t log_len = 0;
+  void* mem = nullptr;
+  const void* twf = nullptr;
+  const void* twi = nullptr;
+  int refs = 0;
+  size_t bytes = 0;
+};
+}  // namespace nttk
+
 struct ntt_plan_s {
   int device = 0;
   uint32_t N = 0, log_n = 0, L = 0, word_bits = 0, flags = 0;
-  uint32_t log_n1 = 0;                // column stages (0: single pass)
+  uint32_t log_n1 = 0;                // default column stages (0: single pass)
+  int forced_split = -1;              // NTT_FLAG_SPLIT, or -1
   std::vector<uint64_t> moduli, psi;
   std::vector<uint32_t> cls;          // arithmetic class per limb
   nttk::LimbDev* d_limbs = nullptr;   // device [L]
-  void* d_tables = nullptr;           // device twiddle tables
+  std::vector<nttk::LimbDev> h_limbs; // host copy of the same constants
+  std::vector<const nttk::PrimeTable*> tables;  // shared tables, one per limb
   uint32_t* d_cls_limbs = nullptr;    // device limb lists, concatenated per class
   uint32_t cls_off[3] = {0, 0, 0};
   uint32_t cls_cnt[3] = {0, 0, 0};
@@ -29,8 +47,8 @@ namespace nttk {
 // Column stages used by polymul.  The fused row kernel holds two operands in
 // registers; at 2^14-word rows (1024 threads, at most 128 VGPRs) it would
 // spill, so such plans multiply with a 2^13-word row pass instead.
-inline uint32_t polymul_split(const ntt_plan_s* p) {
-  return (p->log_n1 == 0 && p->log_n == 14) ? 1u : p->log_n1;
+inline uint32_t polymul_split(const ntt_plan_s* p, uint32_t n1) {
+  return (n1 == 0 && p->log_n == 14) ? 1u : n1;
 }
 
 ntt_status fail(ntt_status st, const char* fmt, ...);
@@ -53,7 +71,24 @@ class LaunchTimer {
   hipStream_t s_ = nullptr;
 };
 
-// Split chosen by the tuning cache for this shape, or `fallback`.
-uint32_t tuned_split(uint32_t N, uint32_t L, uint32_t word_bits, uint32_t fallback);
+// Shared twiddle tables (twiddles.cpp).
+uint32_t table_log_len(uint64_t q);
+ntt_status acquire_table(int device, uint64_t q, uint32_t cls, const PrimeTable** out);
+void release_table(const PrimeTable* t);
+size_t resident_table_bytes();
+
+// Tuning table (tune.cpp).
+uint32_t tuned_split_for(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback);
+uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback);
+bool split_valid(int log_n, int n1);
+
+// Split used by one call over `batch` polynomials.
+inline uint32_t call_split(const ntt_plan_s* p, uint32_t batch) {
+  if (p->forced_split >= 0) return (uint32_t)p->forced_split;
+  uint32_t best = 0, cnt = 0;
+  for (uint32_t c = 0; c < 3; ++c)
+    if (p->cls_cnt[c] > cnt) { cnt = p->cls_cnt[c]; best = c; }
+  return tuned_split_for(p->log_n, best, (uint64_t)batch * p->L, p->log_n1);
+}
 
 }  // namespace nttk

@@ -308,47 +308,48 @@ __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int
 }
 
 // ---------------------------------------------------------------------------
-// Row pass.  INV selects the transform direction; TWO_PASS says whether a
-// column pass precedes (forward) or follows (inverse) this kernel.
+// Row pass on one chunk of N2 = 2^LOGN2 words.  `dst`/`src` point at the
+// chunk, `base` = N1 + c is its twiddle base, `tt` the thread's index within
+// the chunk's N2/16 threads, `lds` the chunk's LDS region.  All threads of the
+// workgroup must call it together (it synchronises the workgroup).
+// INV selects the direction; TWO_PASS says whether a column pass precedes
+// (forward) or follows (inverse): then the pass reads/writes the raw
+// intermediate format instead of canonical words, and the inverse leaves the
+// N^-1 scaling to the column pass.
 template <class A, int LOGN2, bool INV, bool TWO_PASS>
-__global__ void __launch_bounds__(RowShape<LOGN2>::BLOCK)
-row_kernel(RowArgs args) {
+__device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
+                                          const typename A::W* __restrict__ src, const LimbDev& ld,
+                                          uint32_t base, uint32_t tt, typename A::V* lds,
+                                          bool valid) {
   using S = RowShape<LOGN2>;
   using V = typename A::V;
   using W = typename A::W;
-  __shared__ V lds_all[S::LDS_ELEMS];
-  const uint32_t ci = threadIdx.x / S::TPC;
-  const uint32_t tt = threadIdx.x & (S::TPC - 1);
-  const ChunkPos cp = chunk_pos(args, blockIdx.x * S::CPW + ci, LOGN2);
-  const LimbDev& ld = args.limbs[cp.limb];
   const A ar(ld);
-  V* lds = lds_all + ci * S::CHUNK_LDS;
-  const W* __restrict__ src = reinterpret_cast<const W*>(args.src) + cp.off;
-  W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + cp.off;
   V v[16];
   if constexpr (!INV) {
     constexpr int H0 = S::hb(0);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const W x = cp.valid ? src[ins_bits(tt, u, H0)] : W(0);
+      const W x = valid ? src[ins_bits(tt, u, H0)] : W(0);
       v[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twf);
-    row_forward_from<A, LOGN2, 0>(ar, v, tw, cp.base, tt, lds);
+    row_forward_from<A, LOGN2, 0>(ar, v, tw, base, tt, lds);
     if constexpr (S::K > 1) {
       // The last round holds 16 consecutive words per thread; re-deal them
       // through LDS so that each store instruction writes contiguous words.
 #pragma unroll
       for (int u = 0; u < 16; ++u) lds[lds_pad((tt << 4) | u)] = v[u];
       __syncthreads();
-      if (cp.valid) {
+      if (valid) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const uint32_t y = tt + u * S::TPC;
           dst[y] = ar.to_word(lds[lds_pad(y)]);
         }
       }
-    } else if (cp.valid) {
+      __syncthreads();
+    } else if (valid) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) dst[u] = ar.to_word(v[u]);
     }
@@ -358,7 +359,7 @@ row_kernel(RowArgs args) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const uint32_t y = tt + u * S::TPC;
-        const W x = cp.valid ? src[y] : W(0);
+        const W x = valid ? src[y] : W(0);
         V t = ar.from_word(x);
         ar.center(t);
         lds[lds_pad(y)] = t;
@@ -370,20 +371,36 @@ row_kernel(RowArgs args) {
     } else {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const W x = cp.valid ? src[u] : W(0);
+        const W x = valid ? src[u] : W(0);
         v[u] = ar.from_word(x);
         ar.center(v[u]);
       }
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twi);
-    row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, v, tw, cp.base, tt, lds, ld);
+    row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, v, tw, base, tt, lds, ld);
     constexpr int H0 = S::hb(0);
-    if (cp.valid) {
+    if (valid) {
 #pragma unroll
       for (int u = 0; u < 16; ++u)
         dst[ins_bits(tt, u, H0)] = TWO_PASS ? ar.to_raw(v[u]) : ar.to_word(v[u]);
     }
   }
+}
+
+template <class A, int LOGN2, bool INV, bool TWO_PASS>
+__global__ void __launch_bounds__(RowShape<LOGN2>::BLOCK)
+row_kernel(RowArgs args) {
+  using S = RowShape<LOGN2>;
+  using V = typename A::V;
+  using W = typename A::W;
+  __shared__ V lds_all[S::LDS_ELEMS];
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+  const ChunkPos cp = chunk_pos(args, blockIdx.x * S::CPW + ci, LOGN2);
+  row_chunk<A, LOGN2, INV, TWO_PASS>(reinterpret_cast<W*>(args.dst) + cp.off,
+                                     reinterpret_cast<const W*>(args.src) + cp.off,
+                                     args.limbs[cp.limb], cp.base, tt,
+                                     lds_all + ci * S::CHUNK_LDS, cp.valid);
 }
 
 // Fused negacyclic product on one row chunk: forward(a), forward(b), pointwise
@@ -439,33 +456,23 @@ polymul_row_kernel(RowArgs args) {
 // Column pass: one thread owns one column of N1 = 2^LOGN1 elements.
 constexpr int kColBlock = 256;
 
+// One column of N1 = 2^LOGN1 words at src[k << log_n2], k < N1, written to the
+// same positions of dst.  Runs all of the column's stages in registers.
 template <class A, int LOGN1, bool INV, bool TWO_PASS>
-__global__ void __launch_bounds__(kColBlock)
-col_kernel(ColArgs args) {
+__device__ __forceinline__ void col_one(typename A::W* __restrict__ dst,
+                                        const typename A::W* __restrict__ src, const LimbDev& ld,
+                                        uint32_t log_n2, bool valid) {
   using V = typename A::V;
   using W = typename A::W;
   using TW = typename A::TW;
   constexpr int N1 = 1 << LOGN1;
-  const uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
-  const bool valid = gid < args.total_cols;
-  const uint32_t g = valid ? gid : 0;
-  const uint32_t n2 = 1u << args.log_n2;
-  const uint32_t r = g & (n2 - 1);
-  const uint32_t rest = g >> args.log_n2;
-  const uint32_t li = rest % args.n_cls;
-  const uint32_t poly = rest / args.n_cls;
-  const uint32_t limb = args.cls_limbs[li];
-  const LimbDev& ld = args.limbs[limb];
   const A ar(ld);
-  const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
-  const W* __restrict__ src = reinterpret_cast<const W*>(args.src) + off;
-  W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + off;
   V v[N1];
   if constexpr (!INV) {
     const NTT_GLOBAL TW* tw = gptr(reinterpret_cast<const TW*>(ld.twf));
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const W x = valid ? src[(uint64_t)k << args.log_n2] : W(0);
+      const W x = valid ? src[(uint64_t)k << log_n2] : W(0);
       v[k] = ar.from_word(x);
     }
 #pragma unroll
@@ -487,13 +494,13 @@ col_kernel(ColArgs args) {
     if (valid) {
 #pragma unroll
       for (int k = 0; k < N1; ++k)
-        dst[(uint64_t)k << args.log_n2] = TWO_PASS ? ar.to_raw(v[k]) : ar.to_word(v[k]);
+        dst[(uint64_t)k << log_n2] = TWO_PASS ? ar.to_raw(v[k]) : ar.to_word(v[k]);
     }
   } else {
     const NTT_GLOBAL TW* tw = gptr(reinterpret_cast<const TW*>(ld.twi));
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const W x = valid ? src[(uint64_t)k << args.log_n2] : W(0);
+      const W x = valid ? src[(uint64_t)k << log_n2] : W(0);
       v[k] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
       ar.center(v[k]);
     }
@@ -521,9 +528,28 @@ col_kernel(ColArgs args) {
     }
     if (valid) {
 #pragma unroll
-      for (int k = 0; k < N1; ++k) dst[(uint64_t)k << args.log_n2] = ar.to_word(v[k]);
+      for (int k = 0; k < N1; ++k) dst[(uint64_t)k << log_n2] = ar.to_word(v[k]);
     }
   }
+}
+
+template <class A, int LOGN1, bool INV, bool TWO_PASS>
+__global__ void __launch_bounds__(kColBlock)
+col_kernel(ColArgs args) {
+  using W = typename A::W;
+  const uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
+  const bool valid = gid < args.total_cols;
+  const uint32_t g = valid ? gid : 0;
+  const uint32_t n2 = 1u << args.log_n2;
+  const uint32_t r = g & (n2 - 1);
+  const uint32_t rest = g >> args.log_n2;
+  const uint32_t li = rest % args.n_cls;
+  const uint32_t poly = rest / args.n_cls;
+  const uint32_t limb = args.cls_limbs[li];
+  const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
+  col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(args.dst) + off,
+                                   reinterpret_cast<const W*>(args.src) + off, args.limbs[limb],
+                                   args.log_n2, valid);
 }
 
 // ---------------------------------------------------------------------------

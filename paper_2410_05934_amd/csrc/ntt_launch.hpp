@@ -121,27 +121,27 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
 
 template <class A>
 hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
-                                hipStream_t s) {
-  const int n = p->log_n, n1 = p->log_n1, n2 = n - n1;
+                         uint32_t split, hipStream_t s) {
+  const int n = p->log_n, n1 = (int)split, n2 = n - n1;
   hipError_t e = hipSuccess;
   if (n1 == 0) {
-    RowArgs a = row_args(p, c, data, data, nullptr, batch);
+    RowArgs a = row_args(p, c, data, data, nullptr, batch, n1);
     e = inv ? launch_row<A, true, false>(n2, a, s) : launch_row<A, false, false>(n2, a, s);
   } else if (n2 == 0) {
-    ColArgs a = col_args(p, c, data, data, batch);
+    ColArgs a = col_args(p, c, data, data, batch, n1);
     e = inv ? launch_col<A, true, false>(n1, a, s) : launch_col<A, false, false>(n1, a, s);
   } else if (!inv) {
-    ColArgs ca = col_args(p, c, data, data, batch);
+    ColArgs ca = col_args(p, c, data, data, batch, n1);
     e = launch_col<A, false, true>(n1, ca, s);
     if (e == hipSuccess) {
-      RowArgs ra = row_args(p, c, data, data, nullptr, batch);
+      RowArgs ra = row_args(p, c, data, data, nullptr, batch, n1);
       e = launch_row<A, false, true>(n2, ra, s);
     }
   } else {
-    RowArgs ra = row_args(p, c, data, data, nullptr, batch);
+    RowArgs ra = row_args(p, c, data, data, nullptr, batch, n1);
     e = launch_row<A, true, true>(n2, ra, s);
     if (e == hipSuccess) {
-      ColArgs ca = col_args(p, c, data, data, batch);
+      ColArgs ca = col_args(p, c, data, data, batch, n1);
       e = launch_col<A, true, true>(n1, ca, s);
     }
   }
@@ -170,8 +170,8 @@ hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a,
 
 template <class A>
 hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
-                              void* ws, uint32_t batch, hipStream_t s) {
-  const int n = p->log_n, n1 = (int)polymul_split(p), n2 = n - n1;
+                       void* ws, uint32_t batch, uint32_t split, hipStream_t s) {
+  const int n = p->log_n, n1 = (int)split, n2 = n - n1;
   hipError_t e;
   if (n1 == 0) {
     RowArgs ra = row_args(p, c, out, a, b, batch, n1);

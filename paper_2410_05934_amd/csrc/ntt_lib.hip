@@ -40,69 +40,7 @@ ntt_status nttk::hip_fail(hipError_t e, const char* what) {
 
 static void clear_error() { g_last_error.clear(); }
 
-// ---------------------------------------------------------------------------
-// Number theory (128-bit products; runs once per plan)
-
-using u128 = unsigned __int128;
-
-static uint64_t nt_mul(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
-
-static uint64_t nt_pow(uint64_t b, uint64_t e, uint64_t q) {
-  uint64_t r = 1 % q;
-  b %= q;
-  for (; e; e >>= 1) {
-    if (e & 1) r = nt_mul(r, b, q);
-    b = nt_mul(b, b, q);
-  }
-  return r;
-}
-
-// Miller-Rabin with the first twelve prime bases: exact for all 64-bit n.
-static bool nt_is_prime(uint64_t n) {
-  static const uint64_t P[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
-  if (n < 2) return false;
-  for (uint64_t p : P) {
-    if (n % p == 0) return n == p;
-  }
-  uint64_t d = n - 1;
-  int s = 0;
-  while (!(d & 1)) {
-    d >>= 1;
-    ++s;
-  }
-  for (uint64_t a : P) {
-    uint64_t x = nt_pow(a, d, n);
-    if (x == 1 || x == n - 1) continue;
-    bool composite = true;
-    for (int i = 1; i < s && composite; ++i) {
-      x = nt_mul(x, x, n);
-      if (x == n - 1) composite = false;
-    }
-    if (composite) return false;
-  }
-  return true;
-}
-
-static uint64_t nt_smallest_nonresidue(uint64_t q) {
-  for (uint64_t g = 2; g < q; ++g)
-    if (nt_pow(g, (q - 1) / 2, q) == q - 1) return g;
-  return 0;
-}
-
-static int ilog2(uint32_t n) {
-  int l = 0;
-  while ((1u << l) < n) ++l;
-  return l;
-}
-
-static uint32_t brv(uint32_t x, int bits) {
-  uint32_t r = 0;
-  for (int i = 0; i < bits; ++i) {
-    r = (r << 1) | (x & 1);
-    x >>= 1;
-  }
-  return r;
-}
+#include "numtheory.hpp"
 
 static ntt_status check_modulus(uint32_t N, uint64_t q, uint32_t word_bits) {
   if (N < 2 || N > (1u << 16) || (N & (N - 1)))
@@ -134,7 +72,7 @@ static uint32_t default_split(int log_n) {
   return (uint32_t)(log_n - 12);           // column pass + 4096-word rows
 }
 
-static bool split_ok(int log_n, int n1) {
+bool nttk::split_valid(int log_n, int n1) {
   if (n1 == 0) return log_n >= 4 && log_n <= 14;
   if (n1 == log_n) return log_n <= 5;
   return n1 >= 1 && n1 <= 5 && (log_n - n1) >= 4 && (log_n - n1) <= 14;
@@ -147,9 +85,8 @@ static double centred(uint64_t w, uint64_t q) {
 static ntt_status build_plan(ntt_plan_s* p, const uint64_t* moduli) {
   const uint32_t N = p->N;
   const int n = p->log_n;
-  // Per-limb class and table layout.
-  size_t tab_bytes = 0;
-  std::vector<size_t> tab_off(p->L);
+  std::vector<LimbDev> limbs(p->L);
+  p->tables.assign(p->L, nullptr);
   for (uint32_t l = 0; l < p->L; ++l) {
     const uint64_t q = moduli[l];
     uint32_t c;
@@ -157,33 +94,24 @@ static ntt_status build_plan(ntt_plan_s* p, const uint64_t* moduli) {
     else if (!(p->flags & NTT_FLAG_FORCE_INT64) && q < kF64LBound) c = 1;
     else c = 2;
     p->cls[l] = c;
-    tab_off[l] = tab_bytes;
-    tab_bytes += (c == 2 ? sizeof(TwI64) : sizeof(double)) * (size_t)N * 2;
-  }
-  std::vector<unsigned char> host(tab_bytes);
-  std::vector<LimbDev> limbs(p->L);
-  std::vector<uint64_t> pw(N), pwi(N);
-  hipError_t e = hipMalloc(&p->d_tables, tab_bytes);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(twiddle tables)");
-  for (uint32_t l = 0; l < p->L; ++l) {
-    const uint64_t q = moduli[l];
+    const PrimeTable* t = nullptr;
+    ntt_status st = acquire_table(p->device, q, c, &t);
+    if (st != NTT_OK) return st;
+    p->tables[l] = t;
+    // psi_N = psi_table^(2^(log_len - n)); the table prefix of length N is T_N.
     const uint64_t psi = root_of(N, q);
     const uint64_t psi_inv = nt_pow(psi, q - 2, q);
     p->psi[l] = psi;
-    pw[0] = pwi[0] = 1;
-    for (uint32_t k = 1; k < N; ++k) {
-      pw[k] = nt_mul(pw[k - 1], psi, q);
-      pwi[k] = nt_mul(pwi[k - 1], psi_inv, q);
-    }
     const uint64_t ninv = nt_pow(N % q, q - 2, q);
-    const uint64_t w1inv = pwi[brv(1, n)];
+    // last inverse stage twiddle: psi^-brv(1) = psi^-(N/2)
+    const uint64_t w1inv = nt_pow(psi_inv, N / 2, q);
     const uint64_t ninvw = nt_mul(ninv, w1inv, q);
     LimbDev& d = limbs[l];
     std::memset(&d, 0, sizeof(d));
     d.q = q;
     d.qd = (double)q;
     d.qinv = 1.0 / (double)q;
-    d.cls = p->cls[l];
+    d.cls = c;
     d.qbits = 64 - __builtin_clzll(q);
     d.bmu = (uint64_t)(((u128)1 << (2 * d.qbits)) / q);
     d.ninv_d = centred(ninv, q);
@@ -192,35 +120,15 @@ static ntt_status build_plan(ntt_plan_s* p, const uint64_t* moduli) {
     d.ninv_s = (uint64_t)(((u128)ninv << 64) / q);
     d.ninvw = ninvw;
     d.ninvw_s = (uint64_t)(((u128)ninvw << 64) / q);
-    unsigned char* base = host.data() + tab_off[l];
-    unsigned char* dbase = static_cast<unsigned char*>(p->d_tables) + tab_off[l];
-    if (d.cls == 2) {
-      TwI64* f = reinterpret_cast<TwI64*>(base);
-      TwI64* iv = f + N;
-      for (uint32_t k = 0; k < N; ++k) {
-        const uint64_t w = pw[brv(k, n)], wi = pwi[brv(k, n)];
-        f[k] = TwI64{w, (uint64_t)(((u128)w << 64) / q)};
-        iv[k] = TwI64{wi, (uint64_t)(((u128)wi << 64) / q)};
-      }
-      d.twf = dbase;
-      d.twi = dbase + sizeof(TwI64) * N;
-    } else {
-      double* f = reinterpret_cast<double*>(base);
-      double* iv = f + N;
-      for (uint32_t k = 0; k < N; ++k) {
-        f[k] = centred(pw[brv(k, n)], q);
-        iv[k] = centred(pwi[brv(k, n)], q);
-      }
-      d.twf = dbase;
-      d.twi = dbase + sizeof(double) * N;
-    }
+    d.twf = t->twf;
+    d.twi = t->twi;
+    (void)n;
   }
-  e = hipMemcpy(p->d_tables, host.data(), tab_bytes, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddle tables)");
-  e = hipMalloc(&p->d_limbs, sizeof(LimbDev) * p->L);
+  hipError_t e = hipMalloc(&p->d_limbs, sizeof(LimbDev) * p->L);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(limb constants)");
   e = hipMemcpy(p->d_limbs, limbs.data(), sizeof(LimbDev) * p->L, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(limb constants)");
+  p->h_limbs = limbs;
   // Limb lists per arithmetic class.
   std::vector<uint32_t> lists;
   for (int c = 0; c < 3; ++c) {
@@ -239,7 +147,7 @@ static ntt_status build_plan(ntt_plan_s* p, const uint64_t* moduli) {
 
 static void free_plan(ntt_plan_s* p) {
   if (!p) return;
-  if (p->d_tables) (void)hipFree(p->d_tables);
+  for (const PrimeTable* t : p->tables) release_table(t);
   if (p->d_limbs) (void)hipFree(p->d_limbs);
   if (p->d_cls_limbs) (void)hipFree(p->d_cls_limbs);
   delete p;
@@ -249,23 +157,24 @@ static void free_plan(ntt_plan_s* p) {
 namespace nttk {
 template <class A>
 hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
-                         hipStream_t s);
+                         uint32_t split, hipStream_t s);
 template <class A>
 hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
                          uint32_t batch, hipStream_t s);
 template <class A>
 hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
-                       void* ws, uint32_t batch, hipStream_t s);
+                       void* ws, uint32_t batch, uint32_t split, hipStream_t s);
 template <class A>
 hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                    uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
 #define NTT_EXTERN_CLASS(A)                                                                   \
   extern template hipError_t transform_cls<A>(const ntt_plan_s*, int, void*, uint32_t, bool,  \
-                                              hipStream_t);                                   \
+                                              uint32_t, hipStream_t);                         \
   extern template hipError_t pointwise_cls<A>(const ntt_plan_s*, int, void*, const void*,     \
                                               const void*, uint32_t, hipStream_t);            \
   extern template hipError_t polymul_cls<A>(const ntt_plan_s*, int, void*, const void*,       \
-                                            const void*, void*, uint32_t, hipStream_t);       \
+                                            const void*, void*, uint32_t, uint32_t,           \
+                                            hipStream_t);                                     \
   extern template hipError_t mac_cls<A>(const ntt_plan_s*, int, void*, const void*,           \
                                         const void*, uint32_t, uint32_t, uint32_t, hipStream_t);
 NTT_EXTERN_CLASS(ArF64S)
@@ -293,8 +202,6 @@ static ntt_status check_plan_batch(ntt_plan_t p, uint32_t batch) {
   if (words >= (1ull << 32)) return fail(NTT_EINVAL, "batch * L * N must be < 2^32 words");
   return NTT_OK;
 }
-
-uint32_t nttk::tuned_split(uint32_t, uint32_t, uint32_t, uint32_t fallback) { return fallback; }
 
 // ArF64S only instantiates with 32-bit words and the others with 64-bit words;
 // a plan never mixes word widths, so the unused pairings are never launched.
@@ -336,10 +243,8 @@ ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* moduli,
   uint32_t n1 = default_split(log_n);
   if (flags & NTT_FLAG_SPLIT_MASK) {
     const int forced = (int)((flags & NTT_FLAG_SPLIT_MASK) >> 8) - 1;
-    if (!split_ok(log_n, forced)) return fail(NTT_EINVAL, "split n1=%d invalid for N=%u", forced, N);
+    if (!split_valid(log_n, forced)) return fail(NTT_EINVAL, "split n1=%d invalid for N=%u", forced, N);
     n1 = (uint32_t)forced;
-  } else {
-    n1 = nttk::tuned_split(N, num_moduli, word_bits, n1);
   }
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -353,6 +258,7 @@ ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* moduli,
   p->word_bits = word_bits;
   p->flags = flags;
   p->log_n1 = n1;
+  p->forced_split = (flags & NTT_FLAG_SPLIT_MASK) ? (int)n1 : -1;
   p->moduli.assign(moduli, moduli + num_moduli);
   p->psi.resize(num_moduli);
   p->cls.resize(num_moduli);
@@ -383,7 +289,14 @@ ntt_status ntt_plan_root(ntt_plan_t plan, uint32_t limb, uint64_t* psi) {
 ntt_status ntt_plan_split(ntt_plan_t plan, uint32_t* log_n1) {
   clear_error();
   if (!plan || !log_n1) return fail(NTT_EINVAL, "null argument");
-  *log_n1 = plan->log_n1;
+  *log_n1 = plan->forced_split >= 0 ? (uint32_t)plan->forced_split : plan->log_n1;
+  return NTT_OK;
+}
+
+ntt_status ntt_plan_split_for(ntt_plan_t plan, uint32_t batch, uint32_t* log_n1) {
+  clear_error();
+  if (!plan || !log_n1) return fail(NTT_EINVAL, "null argument");
+  *log_n1 = call_split(plan, batch);
   return NTT_OK;
 }
 
@@ -401,7 +314,8 @@ ntt_status ntt_forward(ntt_plan_t plan, void* data, uint32_t batch, void* stream
   if (st != NTT_OK) return st;
   if (!data) return fail(NTT_EINVAL, "null data");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, false, s)));
+  const uint32_t split = call_split(plan, batch);
+  NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, false, split, s)));
   return NTT_OK;
 }
 
@@ -411,7 +325,8 @@ ntt_status ntt_inverse(ntt_plan_t plan, void* data, uint32_t batch, void* stream
   if (st != NTT_OK) return st;
   if (!data) return fail(NTT_EINVAL, "null data");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, true, s)));
+  const uint32_t split = call_split(plan, batch);
+  NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, true, split, s)));
   return NTT_OK;
 }
 
@@ -447,14 +362,15 @@ ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b,
   if (out == a || out == b) return fail(NTT_EINVAL, "out must not alias a or b");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = nullptr;
-  const bool need_ws = polymul_split(plan) != 0;
+  const uint32_t split = polymul_split(plan, call_split(plan, batch));
+  const bool need_ws = split != 0;
   if (need_ws) {
     const size_t bytes = ((size_t)batch * plan->L << plan->log_n) * (plan->word_bits / 8);
     hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(polymul workspace)");
   }
   const ntt_status rc = [&]() -> ntt_status {
-    NTT_FOR_CLASSES(plan, (polymul_cls<A>(plan, c, out, a, b, ws, batch, s)));
+    NTT_FOR_CLASSES(plan, (polymul_cls<A>(plan, c, out, a, b, ws, batch, split, s)));
     return NTT_OK;
   }();
   if (need_ws) (void)hipFreeAsync(ws, s);

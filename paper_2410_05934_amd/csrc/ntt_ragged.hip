@@ -1,0 +1,397 @@
+// ntt_ragged.hip -- ragged batches of transforms in one persistent launch.
+//
+// A ragged batch mixes jobs of different N, limb counts and moduli.  The host
+// turns it into a list of work items -- one limb-row of one job each, or up to
+// 16 limb-rows of the same small N and arithmetic class -- sorted largest
+// first.  One persistent kernel per word width is launched with as many
+// workgroups as fit on the chip at once; each workgroup takes the next item
+// from an atomic counter and transforms its row(s) completely:
+//   N <= 2^12      one row pass in LDS/registers (several rows side by side);
+//   N >= 2^13      column pass then row pass inside the same workgroup, the
+//                  intermediate staying in the workgroup's own global memory
+//                  view (written and re-read by the same CU, separated by a
+//                  workgroup barrier).
+// No item waits for another, so every workgroup exits once the counter passes
+// the end of the list.  This is the paper's single-kernel-launch form of the
+// hybrid NTT (Sec. V-D) applied to a batch: the one global synchronisation of
+// each transform becomes a workgroup barrier because a workgroup owns the
+// whole transform.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "ntt_internal.hpp"
+#include "ntt_kernels.hpp"
+
+namespace nttk {
+
+constexpr int kRaggedBlock = 256;
+constexpr int kRaggedRows = 16;
+constexpr int kRaggedLds = 4096 + 256;  // one 2^12 chunk or several smaller ones, padded
+
+struct RaggedJobDev {
+  void* data;
+  const LimbDev* limbs;
+  uint32_t L;
+  uint32_t log_n;
+  uint32_t log_n2;  // row-pass length inside the workgroup (== log_n for one pass)
+  uint32_t inv;
+};
+
+struct RaggedItem {
+  uint32_t job;
+  uint32_t nrows;
+  uint32_t cls;
+  uint32_t log_n;
+  uint32_t log_n2;
+  uint32_t inv;
+  uint32_t rows[kRaggedRows];  // flattened row index b * L + l
+};
+
+template <class A, int LOGN, bool INV>
+__device__ __noinline__ void ragged_single(const RaggedJobDev* jp, const RaggedItem* ip,
+                                           typename A::V* lds) {
+  using S = RowShape<LOGN>;
+  using W = typename A::W;
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+  const bool valid = ci < ip->nrows;
+  const uint32_t row = ip->rows[valid ? ci : 0];
+  W* p = reinterpret_cast<W*>(jp->data) + ((uint64_t)row << LOGN);
+  row_chunk<A, LOGN, INV, false>(p, p, jp->limbs[row % jp->L], 1u, tt, lds + ci * S::CHUNK_LDS,
+                                 valid);
+}
+
+template <class A, int LOGN1, int LOGN2, bool INV>
+__device__ __noinline__ void ragged_two_pass(const RaggedJobDev* jp, const RaggedItem* ip,
+                                             typename A::V* lds) {
+  using S = RowShape<LOGN2>;
+  using W = typename A::W;
+  // Loop bounds are taken from the job at run time: with compile-time trip
+  // counts the compiler interleaves iterations and doubles register use.
+  const uint32_t N1 = 1u << (jp->log_n - jp->log_n2), N2 = 1u << jp->log_n2;
+  const uint32_t row = ip->rows[0];
+  W* p = reinterpret_cast<W*>(jp->data) + ((uint64_t)row << (LOGN1 + LOGN2));
+  const LimbDev& ld = jp->limbs[row % jp->L];
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+  auto columns = [&]() {
+#pragma unroll 1
+    for (uint32_t r = threadIdx.x; r < N2; r += kRaggedBlock)
+      col_one<A, LOGN1, INV, true>(p + r, p + r, ld, LOGN2, true);
+  };
+  auto rows = [&]() {
+#pragma unroll 1
+    for (uint32_t c0 = 0; c0 < N1; c0 += S::CPW) {
+      const uint32_t c = c0 + ci;
+      const bool valid = c < N1;
+      W* q = p + ((uint64_t)(valid ? c : 0) << LOGN2);
+      row_chunk<A, LOGN2, INV, true>(q, q, ld, N1 + c, tt, lds + ci * S::CHUNK_LDS, valid);
+    }
+  };
+  if constexpr (!INV) {
+    columns();
+    __threadfence_block();
+    __syncthreads();
+    rows();
+  } else {
+    rows();
+    __threadfence_block();
+    __syncthreads();
+    columns();
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+template <class A, bool INV>
+__device__ void ragged_dispatch_size(const RaggedJobDev& j, const RaggedItem& it,
+                                     typename A::V* lds) {
+  if (it.log_n2 == it.log_n) {
+    switch (it.log_n) {
+      case 4: ragged_single<A, 4, INV>(&j, &it, lds); break;
+      case 5: ragged_single<A, 5, INV>(&j, &it, lds); break;
+      case 6: ragged_single<A, 6, INV>(&j, &it, lds); break;
+      case 7: ragged_single<A, 7, INV>(&j, &it, lds); break;
+      case 8: ragged_single<A, 8, INV>(&j, &it, lds); break;
+      case 9: ragged_single<A, 9, INV>(&j, &it, lds); break;
+      case 10: ragged_single<A, 10, INV>(&j, &it, lds); break;
+      case 11: ragged_single<A, 11, INV>(&j, &it, lds); break;
+      case 12: ragged_single<A, 12, INV>(&j, &it, lds); break;
+      default: break;
+    }
+  } else if (it.log_n2 == 12) {
+    switch (it.log_n) {
+      case 13: ragged_two_pass<A, 1, 12, INV>(&j, &it, lds); break;
+      case 14: ragged_two_pass<A, 2, 12, INV>(&j, &it, lds); break;
+      case 15: ragged_two_pass<A, 3, 12, INV>(&j, &it, lds); break;
+      case 16: ragged_two_pass<A, 4, 12, INV>(&j, &it, lds); break;
+      default: break;
+    }
+  } else if (it.log_n2 == 11) {
+    switch (it.log_n) {
+      case 13: ragged_two_pass<A, 2, 11, INV>(&j, &it, lds); break;
+      case 14: ragged_two_pass<A, 3, 11, INV>(&j, &it, lds); break;
+      case 15: ragged_two_pass<A, 4, 11, INV>(&j, &it, lds); break;
+      case 16: ragged_two_pass<A, 5, 11, INV>(&j, &it, lds); break;
+      default: break;
+    }
+  }
+}
+
+template <class A>
+__device__ void ragged_dispatch(const RaggedJobDev& j, const RaggedItem& it, double* lds) {
+  using V = typename A::V;
+  V* l = reinterpret_cast<V*>(lds);
+  if (it.inv) ragged_dispatch_size<A, true>(j, it, l);
+  else ragged_dispatch_size<A, false>(j, it, l);
+}
+
+struct RaggedArgs {
+  const RaggedJobDev* jobs;
+  const RaggedItem* items;
+  uint32_t n_items;
+  uint32_t* counter;
+};
+
+// WIDE = false: 32-bit words (class 0); WIDE = true: 64-bit words (classes 1, 2).
+// Four waves per SIMD (at most 128 VGPRs): each tile shape alone fits, and the
+// budget keeps the allocator from trading occupancy for the union of all shapes.
+template <bool WIDE>
+__global__ void __launch_bounds__(kRaggedBlock, 4) ragged_kernel(RaggedArgs args) {
+  __shared__ double lds[kRaggedLds];
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(args.counter, 1u);
+    __syncthreads();
+    const uint32_t idx = s_item;
+    __syncthreads();
+    if (idx >= args.n_items) break;
+    const RaggedItem& it = args.items[idx];
+    const RaggedJobDev& j = args.jobs[it.job];
+    if constexpr (WIDE) {
+      if (it.cls == 1) ragged_dispatch<ArF64L>(j, it, lds);
+      else ragged_dispatch<ArI64>(j, it, lds);
+    } else {
+      ragged_dispatch<ArF64S>(j, it, lds);
+    }
+  }
+}
+
+__global__ void zero_counters(uint32_t* c, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0;
+}
+
+}  // namespace nttk
+
+using namespace nttk;
+
+struct ntt_ragged_s {
+  int device = 0;
+  std::vector<RaggedJobDev> jobs;
+  std::vector<RaggedItem> items;
+  uint32_t n_items[2] = {0, 0};  // [narrow, wide]
+  RaggedJobDev* d_jobs = nullptr;
+  RaggedItem* d_items = nullptr;
+  uint32_t* d_counter = nullptr;  // [2]
+  uint32_t grid[2] = {0, 0};
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::mutex mu;
+};
+
+namespace {
+
+uint32_t ragged_split_for(uint32_t log_n, uint32_t flags) {
+  if (log_n <= 12) return log_n;
+  const uint32_t forced = (flags >> 8) & 0xf;  // NTT_RAGGED_ROW_LOG(n2)
+  if (forced == 11 || forced == 12) return forced;
+  return tuned_ragged_row_log(log_n, 12);
+}
+
+hipError_t launch_all(ntt_ragged_s* r, hipStream_t s, bool timed) {
+  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, s, r->d_counter, 2u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int w = 0; w < 2; ++w) {
+    if (r->n_items[w] == 0) continue;
+    RaggedArgs a;
+    a.jobs = r->d_jobs;
+    a.items = r->d_items + (w == 1 ? r->n_items[0] : 0);
+    a.n_items = r->n_items[w];
+    a.counter = r->d_counter + w;
+    LaunchTimer t(timed ? "ragged" : nullptr, w ? "u64" : "u32", 0, false, false, 0, s);
+    if (w) hipLaunchKernelGGL(ragged_kernel<true>, dim3(r->grid[w]), dim3(kRaggedBlock), 0, s, a);
+    else hipLaunchKernelGGL(ragged_kernel<false>, dim3(r->grid[w]), dim3(kRaggedBlock), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void free_ragged(ntt_ragged_s* r) {
+  if (!r) return;
+  if (r->exec) (void)hipGraphExecDestroy(r->exec);
+  if (r->graph) (void)hipGraphDestroy(r->graph);
+  if (r->d_jobs) (void)hipFree(r->d_jobs);
+  if (r->d_items) (void)hipFree(r->d_items);
+  if (r->d_counter) (void)hipFree(r->d_counter);
+  delete r;
+}
+
+}  // namespace
+
+extern "C" {
+
+ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n, uint32_t flags) {
+  if (!out || !jobs || n == 0) return fail(NTT_EINVAL, "null argument or empty job list");
+  *out = nullptr;
+  ntt_ragged_s* r = new (std::nothrow) ntt_ragged_s();
+  if (!r) return fail(NTT_ENOMEM, "host allocation");
+  r->use_graph = !(flags & NTT_RAGGED_NO_GRAPH);
+  hipError_t e = hipGetDevice(&r->device);
+  if (e != hipSuccess) {
+    free_ragged(r);
+    return hip_fail(e, "hipGetDevice");
+  }
+  std::vector<RaggedItem> wide, narrow;
+  for (uint32_t ji = 0; ji < n; ++ji) {
+    const ntt_job& jb = jobs[ji];
+    if (!jb.plan || !jb.data || jb.batch == 0 || jb.op > 1) {
+      free_ragged(r);
+      return fail(NTT_EINVAL, "job %u: null plan/data, zero batch or bad op", ji);
+    }
+    const ntt_plan_s* p = jb.plan;
+    if (p->device != r->device) {
+      free_ragged(r);
+      return fail(NTT_EINVAL, "job %u: plan lives on another device", ji);
+    }
+    if (p->log_n < 4) {
+      free_ragged(r);
+      return fail(NTT_EINVAL, "job %u: ragged batches need N >= 16", ji);
+    }
+    RaggedJobDev jd;
+    jd.data = jb.data;
+    jd.limbs = p->d_limbs;
+    jd.L = p->L;
+    jd.log_n = p->log_n;
+    jd.log_n2 = ragged_split_for(p->log_n, flags);
+    jd.inv = jb.op;
+    r->jobs.push_back(jd);
+    const uint32_t per = p->log_n <= 12 ? std::min<uint32_t>(kRaggedRows, std::max<uint32_t>(1u, kRaggedBlock / ((1u << p->log_n) / 16)))
+                                        : 1u;
+    // Group rows of the same limb class; rows run b-major then l.
+    for (uint32_t c = 0; c < 3; ++c) {
+      RaggedItem it;
+      std::memset(&it, 0, sizeof(it));
+      it.job = ji;
+      it.cls = c;
+      it.log_n = p->log_n;
+      it.log_n2 = jd.log_n2;
+      it.inv = jb.op;
+      for (uint32_t b = 0; b < jb.batch; ++b) {
+        for (uint32_t l = 0; l < p->L; ++l) {
+          if (p->cls[l] != c) continue;
+          it.rows[it.nrows++] = b * p->L + l;
+          if (it.nrows == per) {
+            (c == 0 ? narrow : wide).push_back(it);
+            it.nrows = 0;
+          }
+        }
+      }
+      if (it.nrows) (c == 0 ? narrow : wide).push_back(it);
+    }
+  }
+  auto cost = [](const RaggedItem& it) { return (uint64_t)it.nrows * it.log_n << it.log_n; };
+  auto by_cost = [&](const RaggedItem& a, const RaggedItem& b) { return cost(a) > cost(b); };
+  std::stable_sort(narrow.begin(), narrow.end(), by_cost);
+  std::stable_sort(wide.begin(), wide.end(), by_cost);
+  r->n_items[0] = (uint32_t)narrow.size();
+  r->n_items[1] = (uint32_t)wide.size();
+  r->items = narrow;
+  r->items.insert(r->items.end(), wide.begin(), wide.end());
+  int cus = 0, per_cu[2] = {0, 0};
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[0], ragged_kernel<false>, kRaggedBlock, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[1], ragged_kernel<true>, kRaggedBlock, 0);
+  if (e != hipSuccess) {
+    free_ragged(r);
+    return hip_fail(e, "occupancy query");
+  }
+  for (int w = 0; w < 2; ++w)
+    r->grid[w] = std::max(1u, std::min<uint32_t>(r->n_items[w], (uint32_t)(cus * std::max(1, per_cu[w]))));
+  e = hipMalloc(&r->d_jobs, sizeof(RaggedJobDev) * r->jobs.size());
+  if (e == hipSuccess) e = hipMalloc(&r->d_items, sizeof(RaggedItem) * std::max<size_t>(1, r->items.size()));
+  if (e == hipSuccess) e = hipMalloc(&r->d_counter, sizeof(uint32_t) * 2);
+  if (e == hipSuccess)
+    e = hipMemcpy(r->d_jobs, r->jobs.data(), sizeof(RaggedJobDev) * r->jobs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !r->items.empty())
+    e = hipMemcpy(r->d_items, r->items.data(), sizeof(RaggedItem) * r->items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_ragged(r);
+    return hip_fail(e, "ragged descriptors");
+  }
+  *out = r;
+  return NTT_OK;
+}
+
+ntt_status ntt_ragged_run(ntt_ragged_t r, void* stream) {
+  if (!r) return fail(NTT_EINVAL, "null ragged batch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(r->mu);
+  if (!r->use_graph) {
+    hipError_t e = launch_all(r, s, true);
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "ragged launch");
+  }
+  if (!r->exec) {
+    // Capture the counter reset and the persistent launch(es) once.
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = launch_all(r, cap, false);
+      e = hipStreamEndCapture(cap, &r->graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_fail(e, "ragged graph capture");
+  }
+  hipError_t e = hipGraphLaunch(r->exec, s);
+  return e == hipSuccess ? NTT_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+ntt_status ntt_ragged_info(ntt_ragged_t r, uint32_t* items, uint32_t* workgroups) {
+  if (!r) return fail(NTT_EINVAL, "null ragged batch");
+  if (items) *items = r->n_items[0] + r->n_items[1];
+  if (workgroups) *workgroups = (r->n_items[0] ? r->grid[0] : 0) + (r->n_items[1] ? r->grid[1] : 0);
+  return NTT_OK;
+}
+
+ntt_status ntt_ragged_destroy(ntt_ragged_t r) {
+  if (!r) return fail(NTT_EINVAL, "null ragged batch");
+  free_ragged(r);
+  return NTT_OK;
+}
+
+ntt_status ntt_batch_ragged(const ntt_job* jobs, uint32_t n, void* stream) {
+  ntt_ragged_t r = nullptr;
+  ntt_status st = ntt_ragged_create(&r, jobs, n, NTT_RAGGED_NO_GRAPH);
+  if (st != NTT_OK) return st;
+  st = ntt_ragged_run(r, stream);
+  // The descriptors must outlive the launch: wait for it before freeing them.
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  free_ragged(r);
+  if (st != NTT_OK) return st;
+  return e == hipSuccess ? NTT_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+}  // extern "C"

@@ -56,7 +56,7 @@ bool stats_enabled() { return g_on.load(std::memory_order_relaxed); }
 
 LaunchTimer::LaunchTimer(const char* kind, const char* cls, int size_log, bool inv, bool two_pass,
                          uint64_t words, hipStream_t s) {
-  if (!stats_enabled()) return;
+  if (!kind || !stats_enabled()) return;
   char name[96];
   snprintf(name, sizeof(name), "%s_%s_%s_log%d%s", kind, inv ? "inv" : "fwd", cls, size_log,
            two_pass ? "_2pass" : "");

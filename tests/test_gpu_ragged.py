@@ -1,0 +1,156 @@
+"""GPU parity of ragged batches (one persistent launch, hipGraph replay) and of
+the autotuner: results must be bit-identical to the oracle whatever the
+schedule.  Chameleon (arXiv 2410.05934), Sec. V-D (single launch)."""
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_05934_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2410_05934_amd as ntt  # noqa: E402
+from paper_2410_05934_amd.tensors import to_device, to_host  # noqa: E402
+
+Q50 = synth.c2_primes(4)
+Q60 = synth.primes_below(1 << 61, 1 << 17, 3)
+Q30 = synth.primes_below(1 << 30, 1 << 17, 2)
+Q32 = synth.primes_below(1 << 32, 1 << 17, 3)
+
+
+def _mixed_jobs(seed):
+    rng = random.Random(seed)
+    specs = []
+    for logn in range(4, 17):
+        for wb in (64, 32):
+            pool = Q32 if wb == 32 else Q50 + Q60 + Q30
+            L = rng.randint(1, 3)
+            mods = rng.sample(pool, L)
+            batch = rng.randint(1, 3)
+            op = rng.randint(0, 1)
+            specs.append((1 << logn, mods, wb, batch, op))
+    return specs
+
+
+def _build(specs, seed):
+    jobs, hosts = [], []
+    for i, (N, mods, wb, batch, op) in enumerate(specs):
+        plan = ntt.Plan(N, mods, wb)
+        h = synth.uniform_poly(seed * 1000 + i, mods, batch, N)
+        jobs.append((plan, op, to_device(h, wb)))
+        hosts.append(h)
+    return jobs, hosts
+
+
+def _expected(specs, hosts):
+    out = []
+    for (N, mods, wb, batch, op), h in zip(specs, hosts):
+        out.append(oracle.forward(h, mods) if op == 0 else oracle.inverse(h, mods))
+    return out
+
+
+def _check(specs, jobs, want):
+    torch.cuda.synchronize()
+    for (N, mods, wb, batch, op), (plan, _, t), w in zip(specs, jobs, want):
+        assert np.array_equal(to_host(t, wb).astype(np.uint64), w), (N, mods, wb, batch, op)
+
+
+@pytest.mark.parametrize("flags", [0, ntt.RAGGED_NO_GRAPH, ntt.ragged_row_log(11),
+                                   ntt.ragged_row_log(12) | ntt.RAGGED_NO_GRAPH])
+def test_ragged_mixed_sizes_classes_widths(flags):
+    specs = _mixed_jobs(1)
+    jobs, hosts = _build(specs, 1)
+    want = _expected(specs, hosts)
+    rb = ntt.RaggedBatch(jobs, flags)
+    items, wgs = rb.info()
+    assert items >= len(specs) and wgs >= 1
+    rb.run()
+    _check(specs, jobs, want)
+
+
+def test_ragged_graph_replays_after_eager_work():
+    """Replay the captured graph several times with eager work in between."""
+    specs = _mixed_jobs(2)
+    jobs, hosts = _build(specs, 2)
+    want = _expected(specs, hosts)
+    rb = ntt.RaggedBatch(jobs)
+    for rep in range(3):
+        for (N, mods, wb, batch, op), (plan, _, t), h in zip(specs, jobs, hosts):
+            t.copy_(to_device(h, wb))          # eager reset of the inputs
+        torch.cuda.synchronize()
+        rb.run()
+        _check(specs, jobs, want)
+
+
+def test_batch_ragged_one_shot_and_plain_launches_agree():
+    specs = _mixed_jobs(3)
+    jobs, hosts = _build(specs, 3)
+    want = _expected(specs, hosts)
+    ntt.batch_ragged(jobs)
+    _check(specs, jobs, want)
+    # the same jobs one launch per polynomial through the plain calls
+    for (N, mods, wb, batch, op), (plan, _, t), h in zip(specs, jobs, hosts):
+        t.copy_(to_device(h, wb))
+        for b in range(batch):
+            (plan.forward if op == 0 else plan.inverse)(t[b:b + 1])
+    _check(specs, jobs, want)
+
+
+def test_c4_shape_sampled():
+    """256 instances, N = 2^(10..16), 1..40 limbs from a 64-prime pool of 30..60 bits;
+    forward then inverse in two ragged batches; sampled rows against the oracle and
+    the round trip checked in full."""
+    inst = synth.c4_instances(0)
+    plans, tens, hosts = [], [], []
+    for i, it in enumerate(inst):
+        p = ntt.Plan(it.N, it.moduli, 64)
+        h = synth.uniform_poly(5000 + i, it.moduli, 1, it.N)
+        plans.append(p)
+        hosts.append(h)
+        tens.append(to_device(h, 64))
+    fwd = ntt.RaggedBatch([(p, ntt.OP_FORWARD, t) for p, t in zip(plans, tens)])
+    inv = ntt.RaggedBatch([(p, ntt.OP_INVERSE, t) for p, t in zip(plans, tens)])
+    fwd.run()
+    torch.cuda.synchronize()
+    rng = random.Random(0)
+    for i in rng.sample(range(len(inst)), 24):
+        got = to_host(tens[i], 64)
+        l = rng.randrange(len(inst[i].moduli))
+        q = inst[i].moduli[l]
+        want = oracle.forward(hosts[i][:, l:l + 1, :], [q])
+        assert np.array_equal(got[:, l:l + 1, :], want), (i, inst[i].N, l)
+    inv.run()
+    torch.cuda.synchronize()
+    for t, h in zip(tens, hosts):
+        assert np.array_equal(to_host(t, 64), h)
+
+
+def test_tuner_records_and_uses_a_valid_split(tmp_path):
+    ntt.tune_clear()
+    mods = Q50[:2]
+    N = 1 << 15
+    best, us = ntt.tune_split(N, mods, 64, 4)
+    assert us > 0
+    plan = ntt.Plan(N, mods, 64)
+    assert plan.split_for(4) == best
+    a = synth.uniform_poly(9, mods, 4, N)
+    d = to_device(a, 64)
+    plan.forward(d)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(d, 64), oracle.forward(a, mods))
+    path = str(tmp_path / "tune.json")
+    ntt.tune_save(path)
+    ntt.tune_clear()
+    assert plan.split_for(4) == plan.split
+    ntt.tune_load(path)
+    assert plan.split_for(4) == best
+    row_log, us2 = ntt.tune_ragged(1 << 16, Q50[:2], 2)
+    assert row_log in (11, 12) and us2 > 0
+    ntt.tune_clear()
