@@ -100,6 +100,14 @@ def run_gpu(args):
     torch.cuda.set_device(dev)
     N, L, P = 1 << 16, 36, 4
     moduli = synth.c2_primes(L)
+    tuned = {}
+    if not args.no_tune:
+        # The autotuner picks the pass split for this shape (and for the pairs
+        # inside polymul) before anything is timed.
+        for batch in (P, P // 2):
+            n1, us = ntt.tune_split(N, moduli, 64, batch)
+            tuned[f"split_b{batch}"] = {"n1": n1, "fwd_inv_us": round(us, 2)}
+        _log(f"[bench] tuned: {tuned}")
     plan = ntt.Plan(N, moduli, 64)
     _log(f"[bench] plan N={N} L={L} split n1={plan.split}; generating inputs")
     host = synth.uniform_poly(args.seed, moduli, P, N)
@@ -173,7 +181,7 @@ def run_gpu(args):
                 "avg_launch_us": round(d["avg_ms"] * 1e3, 2)}
 
     extra = {"breakdown": breakdown, "ms_per_step_with_launch_events": round(ms_events, 4),
-             "rotating_sets": args.sets}
+             "rotating_sets": args.sets, "split_used": plan.split_for(P), "tuned": tuned}
     if not args.no_aux:
         extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
     return value, ms_per_step, roofline, extra
@@ -237,7 +245,70 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
     x1 = to_device(synth.uniform_poly(7, [q1], 1, N), 32)
     t1 = _time(torch, lambda: (p1.forward(x1, stream), p1.inverse(x1, stream)), 200, stream)
     out["c1_fwd_inv_us"] = round(t1 * 1e3, 2)
+    if not args.no_ragged:
+        out["c4_ragged"] = run_ragged(args, torch, ntt, synth, to_device, stream)
+    if not args.no_serving:
+        from paper_2410_05934_amd import serving
+        res = serving.sweep(args.serving_requests, [0.5, 0.9], 64 << 30, 4, args.seed, True)
+        keep = ("offered_rate", "achieved_req_per_s", "p50_ms", "p99_ms", "p99_ms_small",
+                "p99_ms_large", "mean_batch")
+        out["c5_serving"] = {
+            "requests": res["requests"], "budget_bytes": res["budget_bytes"], "streams": res["streams"],
+            "batched_capacity_req_per_s": res["batched"]["capacity_req_per_s"],
+            "serial_capacity_req_per_s": res["serial"]["capacity_req_per_s"],
+            "batched_over_serial_capacity": res["batched_over_serial_capacity"],
+            "batched": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["batched"]["open_loop"]],
+            "serial": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["serial"]["open_loop"]],
+        }
     return out
+
+
+def run_ragged(args, torch, ntt, synth, to_device, stream):
+    """Ragged mix: 256 instances, N = 2^(10+U{0..6}), L = U{1..40} primes of 30..60
+    bits from a 64-prime pool, u64 words.  Forward then inverse of everything as
+    two persistent launches replayed from a hipGraph, against one forward and one
+    inverse call per polynomial (batch 1 each)."""
+    inst = synth.c4_instances(args.seed)
+    if not args.no_tune:
+        big = sorted({it.N for it in inst if it.N >= (1 << 13)})
+        pool = synth.c4_pool(args.seed)
+        for N in big:
+            ntt.tune_ragged(N, [q for q in pool if q < (1 << 50)][:8], 4)
+    plans, tens = [], []
+    words = 0
+    limb_ntts = 0
+    for i, it in enumerate(inst):
+        p = ntt.Plan(it.N, it.moduli, 64)
+        h = synth.uniform_poly(args.seed * 7919 + i, it.moduli, 1, it.N)
+        plans.append(p)
+        tens.append(to_device(h, 64))
+        words += h.size
+        limb_ntts += len(it.moduli)
+    _log(f"[bench] ragged: {len(inst)} instances, {words * 8 / 1e9:.3f} GB, {limb_ntts} limb-rows")
+    fwd = ntt.RaggedBatch([(p, ntt.OP_FORWARD, t) for p, t in zip(plans, tens)])
+    inv = ntt.RaggedBatch([(p, ntt.OP_INVERSE, t) for p, t in zip(plans, tens)])
+    items, wgs = fwd.info()
+
+    def persistent():
+        fwd.run(stream)
+        inv.run(stream)
+
+    def plain():
+        for p, t in zip(plans, tens):
+            p.forward(t, stream)
+        for p, t in zip(plans, tens):
+            p.inverse(t, stream)
+
+    t_pers = _time(torch, persistent, 10, stream)
+    t_plain = _time(torch, plain, 5, stream)
+    n = 2 * limb_ntts
+    return {"instances": len(inst), "gbytes": round(words * 8 / 1e9, 3), "limb_rows": limb_ntts,
+            "items": items, "persistent_workgroups": wgs,
+            "persistent_graph_ms": round(t_pers, 3), "one_launch_per_poly_ms": round(t_plain, 3),
+            "persistent_limb_ntt_per_s": n / (t_pers * 1e-3),
+            "plain_limb_ntt_per_s": n / (t_plain * 1e-3),
+            "persistent_over_plain": round(t_plain / t_pers, 3),
+            "alg_GBps_persistent": round(2 * 2 * words * 8 / (t_pers * 1e-3) / 1e9, 1)}
 
 
 def run_cpu_baseline(args):
@@ -275,6 +346,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "

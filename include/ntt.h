@@ -165,6 +165,89 @@ ntt_status ntt_ragged_destroy(ntt_ragged_t r);
 /* One-shot form: create, run without a graph, wait for `stream`, destroy. */
 ntt_status ntt_batch_ragged(const ntt_job* jobs, uint32_t n, void* stream);
 
+/* ---- Serving: continuous batching of requests ----------------------------- */
+
+/* A request: one operation on `batch` polynomials of N coefficients over the
+ * given moduli ([batch][L][N] words).  a, b (polymul only) and out are either
+ * device pointers to resident operands (NTT_REQ_DEVICE) or host pointers
+ * (preferably pinned) that the server copies in and out (NTT_REQ_HOST).  The
+ * buffers must stay valid until the request completes. */
+#define NTT_REQ_POLYMUL 0u
+#define NTT_REQ_FORWARD 1u
+#define NTT_REQ_INVERSE 2u
+#define NTT_REQ_DEVICE 0u
+#define NTT_REQ_HOST 1u
+typedef struct {
+  uint32_t op;            /* NTT_REQ_POLYMUL / FORWARD / INVERSE */
+  uint32_t N;
+  uint32_t word_bits;     /* 32 or 64 */
+  uint32_t num_moduli;
+  const uint64_t* moduli; /* copied at submit */
+  uint32_t batch;
+  uint32_t memory;        /* NTT_REQ_DEVICE or NTT_REQ_HOST */
+  const void* a;
+  const void* b;          /* polymul only */
+  void* out;              /* may equal a for FORWARD/INVERSE */
+} ntt_request;
+
+/* Completion record of a request (times in seconds on the host's monotonic clock). */
+typedef struct {
+  uint64_t id;
+  int32_t status;         /* NTT_OK, or the error that ended the request */
+  uint32_t batched_with;  /* requests that shared its launch (1 = alone) */
+  double t_submit, t_admit, t_launch, t_done;
+  uint64_t bytes;         /* device bytes it held while in flight */
+  uint64_t launch_id;     /* the launch it was part of (1, 2, ...) */
+} ntt_request_info;
+
+typedef struct {
+  uint64_t submitted, completed, rejected;
+  uint64_t launches;            /* batched launches issued */
+  uint64_t max_inflight_bytes;  /* high-water mark, never above the budget */
+  uint64_t max_inflight_requests;
+  uint64_t budget_bytes;
+  uint64_t plans_cached;
+} ntt_server_counters;
+
+typedef struct ntt_server_s* ntt_server_t;
+
+/* Server flags. */
+#define NTT_SERVER_SERIAL (1u << 0)   /* one request at a time, FIFO, no batching: the baseline */
+#define NTT_SERVER_DRY_RUN (1u << 1)  /* no device work: a batch "completes" after a modelled
+                                         time; admission/batching logic testable without a GPU */
+
+/* Create a server: a host thread that admits requests while their device bytes
+ * fit in budget_bytes (HBM admission), groups admitted requests of the same
+ * shape (op, N, width, moduli) into one launch (continuous batching: requests
+ * that arrive while others run join the next launch), and keeps up to
+ * n_streams launches in flight on separate streams.  Plans and their twiddle
+ * tables stay resident for the server's life.  max_batch caps the polynomials
+ * per launch (0 = 4096); a launch also takes at most 64 requests.  Batched
+ * operands are staged in a per-stream device arena that grows on demand and
+ * is reused in stream order. */
+ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t n_streams,
+                             uint32_t max_batch, uint32_t flags);
+
+/* Queue a request; *id identifies it.  A request larger than the budget is
+ * rejected here with NTT_ENOMEM. */
+ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id);
+
+/* Wait for request `id` (timeout_ms < 0: forever); fills *info and forgets the
+ * request.  NTT_ETIMEOUT if it did not complete in time. */
+ntt_status ntt_server_wait(ntt_server_t s, uint64_t id, ntt_request_info* info, int32_t timeout_ms);
+
+/* Submit reqs[i] at arrival_s[i] seconds after the call starts (a load
+ * generator that runs at native speed; arrival_s must be non-decreasing).
+ * Returns once every request is submitted; ids[i] receives each id (0 for
+ * requests not submitted after an error). */
+ntt_status ntt_server_replay(ntt_server_t s, const ntt_request* reqs, const double* arrival_s,
+                             uint32_t n, uint64_t* ids);
+
+ntt_status ntt_server_counters_get(ntt_server_t s, ntt_server_counters* c);
+
+/* Stop accepting, finish everything queued, join the thread, free everything. */
+ntt_status ntt_server_destroy(ntt_server_t s);
+
 /* ---- Autotuner ------------------------------------------------------------ */
 
 /* Time every admissible pass split for (N, moduli, word_bits) on `batch`

@@ -18,7 +18,9 @@ import threading
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
            "FLAG_FORCE_INT64", "flag_split", "stats_enable", "stats_reset", "stats_collect",
            "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH",
-           "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear"]
+           "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
+           "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
+           "SERVER_SERIAL", "SERVER_DRY_RUN"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libntt.so")
@@ -76,6 +78,12 @@ _SIGS = {
     "ntt_tune_save": [ctypes.c_char_p],
     "ntt_tune_load": [ctypes.c_char_p],
     "ntt_tune_clear": [],
+    "ntt_server_create": [ctypes.POINTER(_vp), _u64, _u32, _u32, _u32],
+    "ntt_server_submit": [_vp, _vp, ctypes.POINTER(_u64)],
+    "ntt_server_wait": [_vp, _u64, _vp, ctypes.c_int32],
+    "ntt_server_replay": [_vp, _vp, ctypes.POINTER(ctypes.c_double), _u32, ctypes.POINTER(_u64)],
+    "ntt_server_counters_get": [_vp, _vp],
+    "ntt_server_destroy": [_vp],
     "ntt_stats_enable": [ctypes.c_int],
     "ntt_stats_reset": [],
     "ntt_stats_collect": [_vp, _u32, ctypes.POINTER(_u32)],
@@ -168,6 +176,97 @@ def tune_load(path: str) -> None:
 
 def tune_clear() -> None:
     _check(lib().ntt_tune_clear(), "ntt_tune_clear")
+
+
+REQ_POLYMUL, REQ_FORWARD, REQ_INVERSE = 0, 1, 2
+REQ_DEVICE, REQ_HOST = 0, 1
+SERVER_SERIAL, SERVER_DRY_RUN = 1, 2
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("op", _u32), ("N", _u32), ("word_bits", _u32), ("num_moduli", _u32),
+                ("moduli", ctypes.POINTER(_u64)), ("batch", _u32), ("memory", _u32),
+                ("a", _vp), ("b", _vp), ("out", _vp)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("id", _u64), ("status", ctypes.c_int32), ("batched_with", _u32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double), ("bytes", _u64),
+                ("launch_id", _u64)]
+
+
+class _ServerCounters(ctypes.Structure):
+    _fields_ = [(n, _u64) for n in ("submitted", "completed", "rejected", "launches",
+                                    "max_inflight_bytes", "max_inflight_requests",
+                                    "budget_bytes", "plans_cached")]
+
+
+class Server:
+    """Continuous-batching request server (C++ thread inside libntt.so)."""
+
+    def __init__(self, budget_bytes: int, n_streams: int = 4, max_batch: int = 0, flags: int = 0):
+        h = _vp()
+        _check(lib().ntt_server_create(ctypes.byref(h), int(budget_bytes), n_streams, max_batch, flags),
+               "ntt_server_create")
+        self._h = h
+
+    def submit(self, op: int, N: int, moduli, word_bits: int, batch: int, a=0, b=0, out=0,
+               memory: int = REQ_DEVICE) -> int:
+        """a, b, out: device (or host) addresses as ints; returns the request id."""
+        mods = (_u64 * len(moduli))(*[int(q) for q in moduli])
+        r = _Request(op, N, word_bits, len(moduli), ctypes.cast(mods, ctypes.POINTER(_u64)), batch,
+                     memory, a or None, b or None, out or None)
+        rid = _u64()
+        _check(lib().ntt_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "ntt_server_submit")
+        return int(rid.value)
+
+    def replay(self, requests, arrivals) -> list:
+        """requests: list of (op, N, moduli, word_bits, batch, a, b, out[, memory]);
+        arrivals: seconds after the call starts.  Submits at native speed."""
+        n = len(requests)
+        arr = (_Request * n)()
+        keep = []
+        for i, r in enumerate(requests):
+            op, N, moduli, wb, batch, a, b, out = r[:8]
+            memory = r[8] if len(r) > 8 else REQ_DEVICE
+            mods = (_u64 * len(moduli))(*[int(q) for q in moduli])
+            keep.append(mods)
+            arr[i] = _Request(op, N, wb, len(moduli), ctypes.cast(mods, ctypes.POINTER(_u64)), batch,
+                              memory, a or None, b or None, out or None)
+        times = (ctypes.c_double * n)(*[float(t) for t in arrivals])
+        ids = (_u64 * n)()
+        _check(lib().ntt_server_replay(self._h, ctypes.cast(arr, _vp), times, n, ids), "ntt_server_replay")
+        return [int(x) for x in ids]
+
+    def wait(self, rid: int, timeout_ms: int = -1) -> dict:
+        info = _RequestInfo()
+        _check(lib().ntt_server_wait(self._h, rid, ctypes.byref(info), timeout_ms), "ntt_server_wait")
+        return {"id": int(info.id), "status": int(info.status), "batched_with": int(info.batched_with),
+                "t_submit": info.t_submit, "t_admit": info.t_admit, "t_launch": info.t_launch,
+                "t_done": info.t_done, "bytes": int(info.bytes), "launch_id": int(info.launch_id)}
+
+    def counters(self) -> dict:
+        c = _ServerCounters()
+        _check(lib().ntt_server_counters_get(self._h, ctypes.byref(c)), "ntt_server_counters_get")
+        return {n: int(getattr(c, n)) for n, _ in _ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ntt_server_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class KernelStat(ctypes.Structure):

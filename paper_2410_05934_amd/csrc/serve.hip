@@ -1,0 +1,534 @@
+// serve.hip -- continuous batching of NTT / polymul requests on one GPU.
+//
+// A host thread owns the device side.  Requests wait in a FIFO; the thread
+// admits the oldest request whose device bytes fit under the HBM budget
+// (bytes of requests already in flight are still held), then pulls every
+// other waiting request of the same shape (op, N, word width, moduli) that
+// also fits, up to max_batch polynomials, and issues them as ONE launch:
+// gather kernel -> the library's batched transform/polymul -> scatter kernel,
+// on one of n_streams streams.  Requests that arrive while launches run are
+// admitted as memory and stream slots free up, so their work overlaps on the
+// device.  Plans (and their twiddle tables) are created on first use and stay
+// resident.  The batched arithmetic is the same per polynomial as alone, so a
+// request's result does not depend on what it was batched with.
+//
+// The paper batches the TFHE CMux of all ciphertexts into one gate per key bit
+// (Sec. IV-A, Tab. lut-opt) to raise utilisation and cut launches; this server
+// does the same for independent requests arriving over time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "ntt_internal.hpp"
+
+namespace nttk {
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int kMaxCopies = 96;  // descriptors per gather/scatter launch (kernel-argument payload)
+
+struct CopyDesc {
+  uint64_t* dst;
+  const uint64_t* src;
+  uint64_t n64;  // 8-byte units
+};
+struct CopyList {
+  CopyDesc d[kMaxCopies];
+  uint32_t n;
+};
+
+__global__ void copy_list_kernel(CopyList list) {
+  const CopyDesc c = list.d[blockIdx.y];
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < c.n64;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    c.dst[i] = c.src[i];
+}
+
+hipError_t copy_many(const std::vector<CopyDesc>& v, hipStream_t s) {
+  for (size_t off = 0; off < v.size(); off += kMaxCopies) {
+    CopyList l;
+    l.n = (uint32_t)std::min<size_t>(kMaxCopies, v.size() - off);
+    uint64_t mx = 0;
+    for (uint32_t i = 0; i < l.n; ++i) {
+      l.d[i] = v[off + i];
+      mx = std::max(mx, l.d[i].n64);
+    }
+    const uint32_t bx = (uint32_t)std::min<uint64_t>(256, (mx + 255) / 256);
+    hipLaunchKernelGGL(copy_list_kernel, dim3(std::max(1u, bx), l.n), dim3(256), 0, s, l);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+struct Req {
+  uint64_t id = 0;
+  ntt_request r{};
+  std::vector<uint64_t> moduli;
+  uint64_t words = 0;   // batch * L * N
+  uint64_t bytes = 0;   // device bytes held while in flight
+  ntt_request_info info{};
+  bool done = false;
+};
+
+struct Batch {
+  std::vector<Req*> reqs;
+  uint64_t launch_id = 0;
+  int stream = 0;
+  hipEvent_t ev = nullptr;
+  uint64_t bytes = 0;
+  double t_ready = 0;  // dry run: modelled completion time
+};
+
+using ShapeKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, std::vector<uint64_t>>;
+
+ShapeKey shape_of(const Req* q) {
+  return ShapeKey(q->r.op, q->r.N, q->r.word_bits, q->r.memory, q->moduli);
+}
+
+}  // namespace
+}  // namespace nttk
+
+using namespace nttk;
+
+struct ntt_server_s {
+  uint64_t budget = 0;
+  uint32_t n_streams = 1;
+  uint32_t max_batch = 4096;
+  uint32_t flags = 0;
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<int> stream_load;
+  // Per-stream staging arena, grown on demand and reused in stream order (a
+  // later batch on the same stream runs after the earlier one's scatter).
+  std::vector<void*> arena;
+  std::vector<size_t> arena_bytes;
+  uint32_t max_reqs = 64;  // requests per launch
+  std::map<std::tuple<uint32_t, uint32_t, std::vector<uint64_t>>, ntt_plan_t> plans;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> pending;
+  std::unordered_map<uint64_t, Req*> reqs;
+  std::vector<Batch*> inflight;
+  uint64_t inflight_bytes = 0;
+  uint64_t next_id = 1;
+  bool stopping = false;
+  ntt_server_counters ctr{};
+  std::thread th;
+
+  bool serial() const { return flags & NTT_SERVER_SERIAL; }
+  bool dry() const { return flags & NTT_SERVER_DRY_RUN; }
+
+  ntt_plan_t plan_for(const Req* q, ntt_status* st) {
+    auto key = std::make_tuple(q->r.N, q->r.word_bits, q->moduli);
+    auto it = plans.find(key);
+    if (it != plans.end()) return it->second;
+    ntt_plan_t p = nullptr;
+    *st = ntt_plan_create(&p, q->r.N, q->moduli.data(), (uint32_t)q->moduli.size(), q->r.word_bits, 0);
+    if (*st != NTT_OK) return nullptr;
+    plans[key] = p;
+    ctr.plans_cached = plans.size();
+    return p;
+  }
+
+  // Issue one batch (all requests share a shape).  Called with mu held.
+  ntt_status launch(Batch* b) {
+    const double t = now_s();
+    uint32_t polys = 0;
+    for (Req* q : b->reqs) {
+      q->info.t_launch = t;
+      q->info.batched_with = (uint32_t)b->reqs.size();
+      q->info.launch_id = b->launch_id;
+      polys += q->r.batch;
+    }
+    if (dry()) {
+      // Modelled duration: 50 us per launch plus 2 ns per word.
+      uint64_t w = 0;
+      for (Req* q : b->reqs) w += q->words;
+      b->t_ready = t + 50e-6 + 2e-9 * (double)w;
+      return NTT_OK;
+    }
+    hipStream_t s = streams[b->stream];
+    const Req* q0 = b->reqs[0];
+    ntt_status st = NTT_OK;
+    ntt_plan_t plan = plan_for(q0, &st);
+    if (!plan) return st;
+    const uint32_t wb = q0->r.word_bits / 8;
+    const uint64_t per = (uint64_t)q0->moduli.size() * q0->r.N;  // words per polynomial
+    const bool pm = q0->r.op == NTT_REQ_POLYMUL;
+    const bool host = q0->r.memory == NTT_REQ_HOST;
+    const bool single = b->reqs.size() == 1 && !host;
+    hipError_t e = hipSuccess;
+    if (single) {
+      // Operands are resident: run in place on the request's own buffers.
+      const Req* q = q0;
+      if (pm) {
+        st = ntt_polymul(plan, q->r.out, q->r.a, q->r.b, q->r.batch, s);
+      } else {
+        if (q->r.out != q->r.a)
+          e = hipMemcpyAsync(q->r.out, q->r.a, q->words * wb, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+          st = q->r.op == NTT_REQ_FORWARD ? ntt_forward(plan, q->r.out, q->r.batch, s)
+                                           : ntt_inverse(plan, q->r.out, q->r.batch, s);
+      }
+    } else {
+      // Gather every operand into one contiguous batch, run one launch, scatter.
+      const uint64_t total = (uint64_t)polys * per * wb;
+      const size_t need = (size_t)total * (pm ? 3 : 1);
+      if (arena_bytes[b->stream] < need) {
+        // Grow: wait for this stream's earlier batches, then reallocate.
+        e = hipStreamSynchronize(s);
+        if (e == hipSuccess && arena[b->stream]) e = hipFree(arena[b->stream]);
+        arena[b->stream] = nullptr;
+        arena_bytes[b->stream] = 0;
+        const size_t grow = std::max(need, (size_t)64 << 20);
+        if (e == hipSuccess) e = hipMalloc(&arena[b->stream], grow);
+        if (e != hipSuccess) return hip_fail(e, "server staging allocation");
+        arena_bytes[b->stream] = grow;
+      }
+      void* A = arena[b->stream];
+      void* B = pm ? static_cast<unsigned char*>(A) + total : nullptr;
+      void* O = pm ? static_cast<unsigned char*>(A) + 2 * total : nullptr;
+      std::vector<CopyDesc> in;
+      uint64_t off = 0;
+      for (Req* q : b->reqs) {
+        const uint64_t bytes = q->words * wb;
+        unsigned char* da = static_cast<unsigned char*>(A) + off;
+        if (host) {
+          e = hipMemcpyAsync(da, q->r.a, bytes, hipMemcpyHostToDevice, s);
+          if (e == hipSuccess && pm)
+            e = hipMemcpyAsync(static_cast<unsigned char*>(B) + off, q->r.b, bytes,
+                               hipMemcpyHostToDevice, s);
+          if (e != hipSuccess) return hip_fail(e, "server input copy");
+        } else {
+          in.push_back(CopyDesc{reinterpret_cast<uint64_t*>(da), static_cast<const uint64_t*>(q->r.a), bytes / 8});
+          if (pm)
+            in.push_back(CopyDesc{reinterpret_cast<uint64_t*>(static_cast<unsigned char*>(B) + off),
+                                  static_cast<const uint64_t*>(q->r.b), bytes / 8});
+        }
+        off += bytes;
+      }
+      if (!in.empty() && (e = copy_many(in, s)) != hipSuccess) return hip_fail(e, "server gather");
+      void* res = pm ? O : A;
+      if (pm) st = ntt_polymul(plan, O, A, B, polys, s);
+      else st = q0->r.op == NTT_REQ_FORWARD ? ntt_forward(plan, A, polys, s) : ntt_inverse(plan, A, polys, s);
+      if (st != NTT_OK) return st;
+      std::vector<CopyDesc> outc;
+      off = 0;
+      for (Req* q : b->reqs) {
+        const uint64_t bytes = q->words * wb;
+        const unsigned char* src = static_cast<const unsigned char*>(res) + off;
+        if (host) {
+          e = hipMemcpyAsync(q->r.out, src, bytes, hipMemcpyDeviceToHost, s);
+          if (e != hipSuccess) return hip_fail(e, "server output copy");
+        } else {
+          outc.push_back(CopyDesc{static_cast<uint64_t*>(q->r.out), reinterpret_cast<const uint64_t*>(src), bytes / 8});
+        }
+        off += bytes;
+      }
+      if (!outc.empty() && (e = copy_many(outc, s)) != hipSuccess) return hip_fail(e, "server scatter");
+    }
+    if (st != NTT_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "server launch");
+    e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->ev, s);
+    return e == hipSuccess ? NTT_OK : hip_fail(e, "server event");
+  }
+
+  bool batch_done(Batch* b) {
+    if (dry()) return now_s() >= b->t_ready;
+    return hipEventQuery(b->ev) != hipErrorNotReady;
+  }
+
+  void finish(Batch* b, int32_t status) {
+    const double t = now_s();
+    for (Req* q : b->reqs) {
+      q->info.t_done = t;
+      q->info.status = status;
+      q->done = true;
+      ctr.completed += 1;
+    }
+    inflight_bytes -= b->bytes;
+    stream_load[b->stream] -= 1;
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    delete b;
+  }
+
+  int pick_stream() {
+    int best = 0;
+    for (int i = 1; i < (int)stream_load.size(); ++i)
+      if (stream_load[i] < stream_load[best]) best = i;
+    return best;
+  }
+
+  // Form batches under the lock: reserve their bytes and stream slots.
+  void admit(std::vector<Batch*>* out) {
+    const uint32_t slots = serial() ? 1u : n_streams * 2u;
+    while (!pending.empty() && inflight.size() < slots) {
+      // Oldest request that fits in the budget.
+      auto it = pending.begin();
+      if (!serial()) {
+        while (it != pending.end() && inflight_bytes + (*it)->bytes > budget) ++it;
+      } else if (inflight_bytes + (*it)->bytes > budget) {
+        it = pending.end();
+      }
+      if (it == pending.end()) break;
+      Batch* b = new Batch();
+      Req* head = *it;
+      pending.erase(it);
+      b->reqs.push_back(head);
+      b->bytes = head->bytes;
+      uint32_t polys = head->r.batch;
+      if (!serial()) {
+        const ShapeKey key = shape_of(head);
+        for (auto jt = pending.begin(); jt != pending.end();) {
+          Req* q = *jt;
+          if (b->reqs.size() >= max_reqs) break;
+          if (polys + q->r.batch <= max_batch && inflight_bytes + b->bytes + q->bytes <= budget &&
+              shape_of(q) == key) {
+            b->reqs.push_back(q);
+            b->bytes += q->bytes;
+            polys += q->r.batch;
+            jt = pending.erase(jt);
+          } else {
+            ++jt;
+          }
+        }
+      }
+      const double t = now_s();
+      for (Req* q : b->reqs) q->info.t_admit = t;
+      b->stream = pick_stream();
+      stream_load[b->stream] += 1;
+      inflight_bytes += b->bytes;
+      ctr.max_inflight_bytes = std::max(ctr.max_inflight_bytes, inflight_bytes);
+      ctr.launches += 1;
+      b->launch_id = ctr.launches;
+      inflight.push_back(b);
+      uint64_t nreq = 0;
+      for (Batch* x : inflight) nreq += x->reqs.size();
+      ctr.max_inflight_requests = std::max(ctr.max_inflight_requests, nreq);
+      out->push_back(b);
+    }
+  }
+
+  // The device work (HIP calls) runs without the lock, so submitters never
+  // wait behind a launch; only the server thread touches `inflight`, the
+  // streams and the plan cache.
+  void loop() {
+    std::vector<Batch*> done, launched, failed;
+    std::vector<ntt_status> fail_st;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        if (inflight.empty() && pending.empty()) {
+          if (stopping) break;
+          cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
+          continue;
+        }
+      }
+      done.clear();
+      for (Batch* b : inflight)
+        if (batch_done(b)) done.push_back(b);
+      launched.clear();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (Batch* b : done) {
+          inflight.erase(std::find(inflight.begin(), inflight.end(), b));
+          finish(b, NTT_OK);
+        }
+        if (!done.empty()) cv_done.notify_all();
+        admit(&launched);
+      }
+      failed.clear();
+      fail_st.clear();
+      for (Batch* b : launched) {
+        const ntt_status st = launch(b);
+        if (st != NTT_OK) {
+          failed.push_back(b);
+          fail_st.push_back(st);
+        }
+      }
+      if (!failed.empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t i = 0; i < failed.size(); ++i) {
+          inflight.erase(std::find(inflight.begin(), inflight.end(), failed[i]));
+          finish(failed[i], fail_st[i]);
+        }
+        cv_done.notify_all();
+      }
+      if (done.empty() && launched.empty()) {
+        std::unique_lock<std::mutex> lk(mu);
+        // Poll in-flight work; wake early for new arrivals.
+        cv_work.wait_for(lk, std::chrono::microseconds(20));
+      }
+    }
+  }
+};
+
+extern "C" {
+
+ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t n_streams,
+                             uint32_t max_batch, uint32_t flags) {
+  if (!out || budget_bytes == 0 || n_streams == 0 || n_streams > 64)
+    return fail(NTT_EINVAL, "bad server arguments");
+  *out = nullptr;
+  ntt_server_s* s = new (std::nothrow) ntt_server_s();
+  if (!s) return fail(NTT_ENOMEM, "host allocation");
+  s->budget = budget_bytes;
+  s->n_streams = n_streams;
+  s->max_batch = max_batch ? max_batch : 4096;
+  s->flags = flags;
+  s->ctr.budget_bytes = budget_bytes;
+  s->stream_load.assign(n_streams, 0);
+  s->arena.assign(n_streams, nullptr);
+  s->arena_bytes.assign(n_streams, 0);
+  if (!s->dry()) {
+    hipError_t e = hipGetDevice(&s->device);
+    // Staging buffers come from the device's default stream-ordered pool; keep
+    // freed blocks cached there (no release to the driver at synchronisation
+    // points), so a launch's staging allocation is a pool hit.
+    hipMemPool_t pool = nullptr;
+    if (e == hipSuccess && hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) {
+      uint64_t keep = budget_bytes;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    for (uint32_t i = 0; e == hipSuccess && i < n_streams; ++i) {
+      hipStream_t st = nullptr;
+      e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e == hipSuccess) s->streams.push_back(st);
+    }
+    if (e != hipSuccess) {
+      for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+      delete s;
+      return hip_fail(e, "server streams");
+    }
+  }
+  s->th = std::thread([s] {
+    if (!s->dry()) (void)hipSetDevice(s->device);
+    s->loop();
+  });
+  *out = s;
+  return NTT_OK;
+}
+
+ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id) {
+  if (!s || !r || !id) return fail(NTT_EINVAL, "null argument");
+  if (r->op > NTT_REQ_INVERSE || r->batch == 0 || !r->moduli || r->num_moduli == 0 ||
+      (r->memory != NTT_REQ_DEVICE && r->memory != NTT_REQ_HOST))
+    return fail(NTT_EINVAL, "bad request");
+  if (!s->dry() && (!r->a || !r->out || (r->op == NTT_REQ_POLYMUL && !r->b)))
+    return fail(NTT_EINVAL, "null operand");
+  for (uint32_t l = 0; l < r->num_moduli; ++l) {
+    const ntt_status st = ntt_check_modulus(r->N, r->moduli[l], r->word_bits);
+    if (st != NTT_OK) return st;
+  }
+  Req* q = new (std::nothrow) Req();
+  if (!q) return fail(NTT_ENOMEM, "host allocation");
+  q->r = *r;
+  q->moduli.assign(r->moduli, r->moduli + r->num_moduli);
+  q->r.moduli = nullptr;
+  q->words = (uint64_t)r->batch * r->num_moduli * r->N;
+  const uint64_t opnd = q->words * (r->word_bits / 8);
+  // Device bytes while in flight: staging for inputs and output (+ the
+  // polymul workspace when the transform has a column pass).
+  const uint64_t nbuf = r->op == NTT_REQ_POLYMUL ? 4 : 2;
+  q->bytes = opnd * nbuf;
+  std::lock_guard<std::mutex> lk(s->mu);
+  q->id = s->next_id++;
+  q->info.id = q->id;
+  q->info.t_submit = now_s();
+  q->info.bytes = q->bytes;
+  s->ctr.submitted += 1;
+  if (q->bytes > s->budget) {
+    s->ctr.rejected += 1;
+    delete q;
+    return fail(NTT_ENOMEM, "request needs %llu bytes, budget is %llu",
+                (unsigned long long)q->bytes, (unsigned long long)s->budget);
+  }
+  if (s->stopping) {
+    delete q;
+    return fail(NTT_EBUSY, "server is stopping");
+  }
+  s->reqs[q->id] = q;
+  s->pending.push_back(q);
+  *id = q->id;
+  s->cv_work.notify_one();
+  return NTT_OK;
+}
+
+ntt_status ntt_server_wait(ntt_server_t s, uint64_t id, ntt_request_info* info, int32_t timeout_ms) {
+  if (!s) return fail(NTT_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(NTT_EINVAL, "unknown request %llu", (unsigned long long)id);
+  Req* q = it->second;
+  auto ready = [&] { return q->done; };
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+    return fail(NTT_ETIMEOUT, "request %llu not done", (unsigned long long)id);
+  }
+  if (info) *info = q->info;
+  const int32_t st = q->info.status;
+  s->reqs.erase(it);
+  delete q;
+  return st == NTT_OK ? NTT_OK : (ntt_status)st;
+}
+
+ntt_status ntt_server_replay(ntt_server_t s, const ntt_request* reqs, const double* arrival_s,
+                             uint32_t n, uint64_t* ids) {
+  if (!s || !reqs || !arrival_s || !ids) return fail(NTT_EINVAL, "null argument");
+  const double t0 = now_s();
+  for (uint32_t i = 0; i < n; ++i) {
+    const double due = t0 + arrival_s[i];
+    while (now_s() < due) {
+    }
+    const ntt_status st = ntt_server_submit(s, &reqs[i], &ids[i]);
+    if (st != NTT_OK) {
+      for (uint32_t j = i; j < n; ++j) ids[j] = 0;
+      return st;
+    }
+  }
+  return NTT_OK;
+}
+
+ntt_status ntt_server_counters_get(ntt_server_t s, ntt_server_counters* c) {
+  if (!s || !c) return fail(NTT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *c = s->ctr;
+  return NTT_OK;
+}
+
+ntt_status ntt_server_destroy(ntt_server_t s) {
+  if (!s) return fail(NTT_EINVAL, "null server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    s->cv_work.notify_all();
+  }
+  if (s->th.joinable()) s->th.join();
+  for (auto& kv : s->reqs) delete kv.second;
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  for (void* a : s->arena)
+    if (a) (void)hipFree(a);
+  for (auto& kv : s->plans) ntt_plan_destroy(kv.second);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+  return NTT_OK;
+}
+
+}  // extern "C"

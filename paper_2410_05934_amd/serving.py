@@ -1,0 +1,130 @@
+"""Load driver for the request server: Poisson arrivals of polymul requests,
+latency percentiles and throughput, continuous batching against a serial FIFO.
+
+Request mix (the serving configuration): 70% are 1..64 polymul pairs at
+N = 2^10 over one 32-bit prime (32-bit words); 30% are one pair at N = 2^16 over
+the first L = 8..36 of the ~50-bit primes (64-bit words).  Operands are resident
+on the device (inputs shared per shape, one output buffer per request); the
+server admits requests by its HBM budget and batches same-shape requests.
+
+    python -m paper_2410_05934_amd.serving --requests 10000 --fractions 0.1,0.5,0.9,1.2
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+import numpy as np
+
+from . import synth
+
+
+class Workload:
+    """Device operands for a list of requests."""
+
+    def __init__(self, reqs, seed: int = 0):
+        import torch
+        from .tensors import empty_device, to_device
+        self.reqs = reqs
+        self.inputs = {}
+        self.outs = []
+        for r in reqs:
+            key = (r.N, len(r.moduli), r.pairs, r.word_bits)
+            if key not in self.inputs:
+                a = synth.uniform_poly(synth.derive_seed(seed, r.N, len(r.moduli), r.pairs, 1), r.moduli, r.pairs, r.N)
+                b = synth.uniform_poly(synth.derive_seed(seed, r.N, len(r.moduli), r.pairs, 2), r.moduli, r.pairs, r.N)
+                self.inputs[key] = (to_device(a, r.word_bits), to_device(b, r.word_bits), a, b)
+            self.outs.append(empty_device((r.pairs, len(r.moduli), r.N), r.word_bits))
+        torch.cuda.synchronize()
+
+    def operands(self, i):
+        r = self.reqs[i]
+        da, db, _, _ = self.inputs[(r.N, len(r.moduli), r.pairs, r.word_bits)]
+        return da, db, self.outs[i]
+
+
+def run_load(server, work: Workload, rate: float | None, ntt_mod) -> dict:
+    """Replay every request at its arrival time (rate None: all at t = 0, a
+    burst) through the library's native load generator, then collect the
+    completion records and return latency statistics."""
+    reqs = work.reqs
+    n = len(reqs)
+    gaps = np.diff([0.0] + [r.arrival_s for r in reqs])
+    base_rate = n / max(reqs[-1].arrival_s, 1e-9)
+    scale = 0.0 if rate is None else base_rate / rate
+    arrivals = np.cumsum(gaps * scale)
+    batch = []
+    for i, r in enumerate(reqs):
+        da, db, out = work.operands(i)
+        batch.append((ntt_mod.REQ_POLYMUL, r.N, r.moduli, r.word_bits, r.pairs,
+                      da.data_ptr(), db.data_ptr(), out.data_ptr()))
+    ids = server.replay(batch, arrivals)
+    infos = [server.wait(i, 600000) for i in ids]
+    lat = np.array([x["t_done"] - x["t_submit"] for x in infos])
+    t_first = min(x["t_submit"] for x in infos)
+    t_last = max(x["t_done"] for x in infos)
+    big = np.array([r.N == (1 << 16) for r in reqs])
+    c = server.counters()
+    return {
+        "requests": n,
+        "offered_rate": rate,
+        "achieved_req_per_s": n / (t_last - t_first),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "p50_ms_small": float(np.percentile(lat[~big], 50) * 1e3) if (~big).any() else None,
+        "p99_ms_small": float(np.percentile(lat[~big], 99) * 1e3) if (~big).any() else None,
+        "p50_ms_large": float(np.percentile(lat[big], 50) * 1e3) if big.any() else None,
+        "p99_ms_large": float(np.percentile(lat[big], 99) * 1e3) if big.any() else None,
+        "mean_batch": float(np.mean([x["batched_with"] for x in infos])),
+        "launches": c["launches"],
+        "max_inflight_bytes": c["max_inflight_bytes"],
+    }
+
+
+def sweep(n_requests: int, fractions, budget: int = 64 << 30, streams: int = 4, seed: int = 0,
+          serial_too: bool = True) -> dict:
+    import paper_2410_05934_amd as ntt
+    reqs = synth.c5_requests(seed, n_requests, 1000.0)
+    work = Workload(reqs, seed)
+    out = {"budget_bytes": budget, "streams": streams, "requests": n_requests}
+    modes = [("batched", 0)] + ([("serial", ntt.SERVER_SERIAL)] if serial_too else [])
+    for name, flags in modes:
+        with ntt.Server(budget, streams, 0, flags) as srv:
+            # warm-up: plans and twiddles resident, pools grown
+            run_load(srv, _subset(work, 256), None, ntt)
+            cap = run_load(srv, work, None, ntt)
+            res = {"capacity_req_per_s": cap["achieved_req_per_s"], "burst": cap, "open_loop": []}
+            for f in fractions:
+                rate = f * cap["achieved_req_per_s"]
+                res["open_loop"].append({"fraction": f, **run_load(srv, work, rate, ntt)})
+            out[name] = res
+    if serial_too:
+        out["batched_over_serial_capacity"] = (out["batched"]["capacity_req_per_s"]
+                                               / out["serial"]["capacity_req_per_s"])
+    return out
+
+
+def _subset(work: Workload, k: int) -> Workload:
+    w = Workload.__new__(Workload)
+    w.reqs = work.reqs[:k]
+    w.inputs = work.inputs
+    w.outs = work.outs[:k]
+    return w
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--fractions", default="0.1,0.3,0.5,0.7,0.9,1.1,1.2")
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-serial", action="store_true")
+    args = ap.parse_args()
+    res = sweep(args.requests, [float(x) for x in args.fractions.split(",")],
+                int(args.budget_gb * (1 << 30)), args.streams, args.seed, not args.no_serial)
+    print(json.dumps(res, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,95 @@
+"""GPU tests of the request server: every result equals the oracle's and is
+the same alone (serial server) and in the mix (continuous batching)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_05934_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2410_05934_amd as ntt  # noqa: E402
+from paper_2410_05934_amd.tensors import empty_device, to_device, to_host  # noqa: E402
+
+
+def _requests(n, seed):
+    """A serving mix with its own inputs per request (small limb counts keep the oracle quick)."""
+    small_q = synth.c3_prime()
+    big = synth.c2_primes(6)
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        if rng.random() < 0.7:
+            N, mods, wb, pairs = 1 << 10, [small_q], 32, int(rng.integers(1, 9))
+        else:
+            N, mods, wb, pairs = 1 << 16, big[: int(rng.integers(1, 4))], 64, 1
+        op = [ntt.REQ_POLYMUL, ntt.REQ_FORWARD, ntt.REQ_INVERSE][int(rng.integers(0, 3))] if i % 4 == 0 else ntt.REQ_POLYMUL
+        a = synth.uniform_poly(seed * 100000 + 2 * i, mods, pairs, N)
+        b = synth.uniform_poly(seed * 100000 + 2 * i + 1, mods, pairs, N)
+        out.append((op, N, mods, wb, pairs, a, b))
+    return out
+
+
+def _want(req):
+    op, N, mods, wb, pairs, a, b = req
+    if op == ntt.REQ_POLYMUL:
+        return oracle.polymul(a, b, mods)
+    if op == ntt.REQ_FORWARD:
+        return oracle.forward(a, mods)
+    return oracle.inverse(a, mods)
+
+
+def _run(reqs, flags, streams=4, budget=8 << 30, memory=ntt.REQ_DEVICE):
+    results = []
+    bufs, ptr_list = [], []
+    for op, N, mods, wb, pairs, a, b in reqs:
+        if memory == ntt.REQ_DEVICE:
+            da, db = to_device(a, wb), to_device(b, wb)
+            out = empty_device(a.shape, wb)
+        else:
+            dt = np.uint64 if wb == 64 else np.uint32
+            da = torch.from_numpy(a.astype(dt).view(np.int64 if wb == 64 else np.int32)).pin_memory()
+            db = torch.from_numpy(b.astype(dt).view(np.int64 if wb == 64 else np.int32)).pin_memory()
+            out = torch.empty_like(da).pin_memory()
+        bufs.append((da, db, out))
+        ptr_list.append((da.data_ptr(), db.data_ptr(), out.data_ptr()))
+    torch.cuda.synchronize()
+    with ntt.Server(budget, streams, 0, flags) as srv:
+        # all buffers exist before the first submit: the requests arrive as a burst
+        ids = [srv.submit(op, N, mods, wb, pairs, *ptrs, memory=memory)
+               for (op, N, mods, wb, pairs, a, b), ptrs in zip(reqs, ptr_list)]
+        infos = [srv.wait(i, 120000) for i in ids]
+        counters = srv.counters()
+    torch.cuda.synchronize()
+    for (op, N, mods, wb, pairs, a, b), (da, db, out) in zip(reqs, bufs):
+        if memory == ntt.REQ_DEVICE:
+            results.append(to_host(out, wb).astype(np.uint64))
+        else:
+            results.append(out.numpy().view(np.uint64 if wb == 64 else np.uint32).astype(np.uint64))
+    return results, infos, counters
+
+
+def test_mix_matches_oracle_and_alone():
+    reqs = _requests(48, 1)
+    mixed, infos, c = _run(reqs, 0, streams=1)
+    alone, infos1, c1 = _run(reqs, ntt.SERVER_SERIAL)
+    assert max(x["batched_with"] for x in infos) > 1, "the mix should have batched something"
+    assert all(x["batched_with"] == 1 for x in infos1)
+    for req, m, s in zip(reqs, mixed, alone):
+        w = _want(req)
+        assert np.array_equal(m, w)
+        assert np.array_equal(s, w)
+    assert c["max_inflight_bytes"] <= c["budget_bytes"]
+
+
+def test_host_memory_requests_and_a_small_budget():
+    reqs = _requests(24, 2)
+    big = max(4 * 8 * r[4] * len(r[2]) * r[1] for r in reqs)
+    got, infos, c = _run(reqs, 0, streams=2, budget=big + (1 << 20), memory=ntt.REQ_HOST)
+    for req, g in zip(reqs, got):
+        assert np.array_equal(g, _want(req))
+    assert c["max_inflight_bytes"] <= big + (1 << 20)
