@@ -336,6 +336,19 @@ def run_cpu_baseline(args):
                       f"{el:.1f} s, {cores} threads over (poly, limb) rows"}
 
 
+def calibrate_copy(gib: int = 1, reps: int = 4) -> None:
+    """A plain device copy of known size, for scaling the HBM byte counters:
+    each launch reads and writes exactly `gib` GiB."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes_each_way": n * 8, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,7 +363,12 @@ def main():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=3000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(every (poly, limb) transform is independent; see the sharding notes). "

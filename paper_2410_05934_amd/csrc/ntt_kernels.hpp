@@ -51,6 +51,7 @@ struct RowArgs {
   uint32_t log_n;            // log2 N
   uint32_t log_n1;           // column stages before this pass (0: single pass)
   uint32_t total_chunks;     // batch * n_cls * N1
+  uint32_t batch;            // polynomials
 };
 
 struct ColArgs {
@@ -291,15 +292,27 @@ struct ChunkPos {
   bool valid;
 };
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumber them so that XCD x runs a contiguous range of chunk indices:
+// chunks are ordered polynomial-fastest, so the polynomials that share a
+// modulus (and its twiddle table) run on one XCD back to back, and each XCD
+// needs the tables of only 1/8 of the limbs.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
+  const uint32_t per = nblocks / kXcds;
+  if (b >= per * kXcds) return b;
+  return (b % kXcds) * per + b / kXcds;
+}
+
 __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int log_n2) {
   ChunkPos p;
   p.valid = gc < a.total_chunks;
   const uint32_t g = p.valid ? gc : 0;
   const uint32_t n1 = 1u << a.log_n1;
-  const uint32_t c = g & (n1 - 1);
-  const uint32_t rest = g >> a.log_n1;
-  const uint32_t li = rest % a.n_cls;
-  const uint32_t poly = rest / a.n_cls;
+  const uint32_t poly = g % a.batch;
+  const uint32_t rest = g / a.batch;
+  const uint32_t c = rest & (n1 - 1);
+  const uint32_t li = rest >> a.log_n1;
   p.limb = a.cls_limbs[li];
   p.off = ((uint64_t)poly * a.L + p.limb) << a.log_n;
   p.off += (uint64_t)c << log_n2;
@@ -396,7 +409,7 @@ row_kernel(RowArgs args) {
   __shared__ V lds_all[S::LDS_ELEMS];
   const uint32_t ci = threadIdx.x / S::TPC;
   const uint32_t tt = threadIdx.x & (S::TPC - 1);
-  const ChunkPos cp = chunk_pos(args, blockIdx.x * S::CPW + ci, LOGN2);
+  const ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
   row_chunk<A, LOGN2, INV, TWO_PASS>(reinterpret_cast<W*>(args.dst) + cp.off,
                                      reinterpret_cast<const W*>(args.src) + cp.off,
                                      args.limbs[cp.limb], cp.base, tt,
@@ -416,7 +429,7 @@ polymul_row_kernel(RowArgs args) {
   __shared__ V lds_all[S::LDS_ELEMS];
   const uint32_t ci = threadIdx.x / S::TPC;
   const uint32_t tt = threadIdx.x & (S::TPC - 1);
-  const ChunkPos cp = chunk_pos(args, blockIdx.x * S::CPW + ci, LOGN2);
+  const ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
   const LimbDev& ld = args.limbs[cp.limb];
   const A ar(ld);
   V* lds = lds_all + ci * S::CHUNK_LDS;

@@ -100,6 +100,7 @@ inline RowArgs row_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.log_n = p->log_n;
   a.log_n1 = (uint32_t)n1;
   a.total_chunks = batch * p->cls_cnt[c] << n1;
+  a.batch = batch;
   return a;
 }
 
