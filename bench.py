@@ -108,7 +108,7 @@ def run_gpu(args):
             n1, us = ntt.tune_split(N, moduli, 64, batch)
             tuned[f"split_b{batch}"] = {"n1": n1, "fwd_inv_us": round(us, 2)}
         _log(f"[bench] tuned: {tuned}")
-    plan = ntt.Plan(N, moduli, 64)
+    plan = ntt.Plan(N, moduli, 64, flags=ntt.FLAG_ROW_RADIX8 if args.row_radix8 else 0)
     _log(f"[bench] plan N={N} L={L} split n1={plan.split}; generating inputs")
     host = synth.uniform_poly(args.seed, moduli, P, N)
     X = [to_device(host, 64) for _ in range(args.sets)]
@@ -362,6 +362,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--row-radix8", action="store_true", help="radix-8 row passes")
     ap.add_argument("--serving-requests", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")

@@ -67,6 +67,9 @@ typedef enum {
 /* Force the 64-bit integer (Shoup) arithmetic for every limb, even where the
  * exact fp64 arithmetic would be chosen (testing and measurement). */
 #define NTT_FLAG_FORCE_INT64 (1u << 16)
+/* Row passes of 2^10 .. 2^13 words with 8 values per thread (radix-8 rounds,
+ * twice the threads of the default radix-16 rounds, one more LDS exchange). */
+#define NTT_FLAG_ROW_RADIX8 (1u << 17)
 
 /* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
  * precomputed per modulus as the paper keeps them in constant memory, Sec. II-E).

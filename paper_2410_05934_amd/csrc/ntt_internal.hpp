@@ -32,6 +32,7 @@ struct ntt_plan_s {
   uint32_t N = 0, log_n = 0, L = 0, word_bits = 0, flags = 0;
   uint32_t log_n1 = 0;                // default column stages (0: single pass)
   int forced_split = -1;              // NTT_FLAG_SPLIT, or -1
+  int row_rb = 0;                     // forced log2 values per thread in row passes (0: choose)
   std::vector<uint64_t> moduli, psi;
   std::vector<uint32_t> cls;          // arithmetic class per limb
   nttk::LimbDev* d_limbs = nullptr;   // device [L]
@@ -82,13 +83,29 @@ uint32_t tuned_split_for(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t f
 uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback);
 bool split_valid(int log_n, int n1);
 
-// Split used by one call over `batch` polynomials.
-inline uint32_t call_split(const ntt_plan_s* p, uint32_t batch) {
-  if (p->forced_split >= 0) return (uint32_t)p->forced_split;
+// Values per thread (log2) of row passes: forced by NTT_FLAG_ROW_RADIX8, else the
+// tuning table, else radix-8 for inverse rows of 2^10..2^13 words (more waves to
+// hide the inverse's early loads) and radix-16 for forward and polymul rows.
+uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback);
+inline int dominant_class(const ntt_plan_s* p) {
   uint32_t best = 0, cnt = 0;
   for (uint32_t c = 0; c < 3; ++c)
     if (p->cls_cnt[c] > cnt) { cnt = p->cls_cnt[c]; best = c; }
-  return tuned_split_for(p->log_n, best, (uint64_t)batch * p->L, p->log_n1);
+  return (int)best;
+}
+inline int row_rb_for(const ntt_plan_s* p, bool inv, uint32_t split, uint32_t batch) {
+  const int n2 = (int)p->log_n - (int)split;
+  if (n2 < 10 || n2 > 13) return 4;
+  if (p->row_rb) return p->row_rb;
+  const uint32_t fallback = inv ? 3u : 4u;
+  return (int)tuned_row_rb(inv ? 3u : 2u, p->log_n, (uint32_t)dominant_class(p),
+                           (uint64_t)batch * p->L, fallback);
+}
+
+// Split used by one call over `batch` polynomials.
+inline uint32_t call_split(const ntt_plan_s* p, uint32_t batch) {
+  if (p->forced_split >= 0) return (uint32_t)p->forced_split;
+  return tuned_split_for(p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L, p->log_n1);
 }
 
 }  // namespace nttk

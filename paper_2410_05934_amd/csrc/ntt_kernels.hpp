@@ -91,19 +91,22 @@ struct MacArgs {
   uint64_t total;            // groups * n_cls * N
 };
 
-template <int LOGN2>
+// Row-chunk geometry: 2^LOGN2 words, R = 2^RB values per thread (radix-R
+// rounds of RB fused stages).
+template <int LOGN2, int RB = 4>
 struct RowShape {
+  static constexpr int R = 1 << RB;
   static constexpr int N2 = 1 << LOGN2;
-  static constexpr int TPC = N2 / 16;  // threads per chunk
+  static constexpr int TPC = N2 / R;  // threads per chunk
   static constexpr int CPW = TPC >= kRowThreadsMin ? 1 : kRowThreadsMin / TPC;
   static constexpr int BLOCK = TPC * CPW;
-  static constexpr int K = (LOGN2 + 3) / 4;  // radix-16 rounds
-  static constexpr int LAST = LOGN2 - 4 * (K - 1);  // stages in the last round
+  static constexpr int K = (LOGN2 + RB - 1) / RB;  // rounds
+  static constexpr int LAST = LOGN2 - RB * (K - 1);  // stages in the last round
   static constexpr int CHUNK_LDS = K > 1 ? N2 + N2 / 16 : 1;
   static constexpr int LDS_ELEMS = CPW * CHUNK_LDS;
   // held-bit offset of round j (forward numbering)
-  static constexpr int hb(int j) { return j < K - 1 ? LOGN2 - 4 - 4 * j : 0; }
-  static constexpr int nst(int j) { return j < K - 1 ? 4 : LAST; }
+  static constexpr int hb(int j) { return j < K - 1 ? LOGN2 - RB - RB * j : 0; }
+  static constexpr int nst(int j) { return j < K - 1 ? RB : LAST; }
 };
 
 #define NTT_GLOBAL __attribute__((address_space(1)))
@@ -115,8 +118,10 @@ __device__ __forceinline__ const NTT_GLOBAL T* gptr(const T* p) {
   return (const NTT_GLOBAL T*)p;
 }
 
+// Local index of value u of thread tt when the thread holds the RB bits at hb.
+template <int RB = 4>
 __device__ __forceinline__ uint32_t ins_bits(uint32_t tt, uint32_t u, int hb) {
-  return ((tt >> hb) << (hb + 4)) | (u << hb) | (tt & ((1u << hb) - 1u));
+  return ((tt >> hb) << (hb + RB)) | (u << hb) | (tt & ((1u << hb) - 1u));
 }
 __device__ __forceinline__ uint32_t lds_pad(uint32_t y) { return y + (y >> 4); }
 
@@ -154,14 +159,14 @@ __device__ __forceinline__ void load_tw(TW (&w)[G], const TW* __restrict__ tab_i
   }
 }
 
-// One forward (CT) stage on the 16 registers: local stage SP acts on u-bit B.
-template <class A, int B, int SP, int HB>
-__device__ __forceinline__ void fwd_stage(const A& ar, typename A::V (&v)[16],
+// One forward (CT) stage on the R registers: local stage SP acts on u-bit B.
+template <class A, int RB, int B, int SP, int HB>
+__device__ __forceinline__ void fwd_stage(const A& ar, typename A::V (&v)[1 << RB],
                                           const typename A::TW* __restrict__ tw, uint32_t base,
                                           uint32_t tt) {
-  constexpr int G = 1 << (3 - B);
+  constexpr int G = 1 << (RB - 1 - B);
   typename A::TW w[G];
-  const uint32_t tg = (base << SP) + ((tt >> HB) << (3 - B));
+  const uint32_t tg = (base << SP) + ((tt >> HB) << (RB - 1 - B));
   load_tw<typename A::TW, G>(w, tw, tg);
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -174,11 +179,11 @@ __device__ __forceinline__ void fwd_stage(const A& ar, typename A::V (&v)[16],
 }
 
 // One inverse (GS) stage; FOLD applies N^-1 (only for global stage 0).
-template <class A, int B, int SP, int HB, bool FOLD>
-__device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[16],
+template <class A, int RB, int B, int SP, int HB, bool FOLD>
+__device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[1 << RB],
                                           const typename A::TW* __restrict__ tw, uint32_t base,
                                           uint32_t tt, const LimbDev& ld) {
-  constexpr int G = 1 << (3 - B);
+  constexpr int G = 1 << (RB - 1 - B);
   if constexpr (FOLD) {
     static_assert(G == 1, "fold only at the single-group stage");
 #pragma unroll
@@ -188,7 +193,7 @@ __device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[16],
     }
   } else {
     typename A::TW w[G];
-    const uint32_t tg = (base << SP) + ((tt >> HB) << (3 - B));
+    const uint32_t tg = (base << SP) + ((tt >> HB) << (RB - 1 - B));
     load_tw<typename A::TW, G>(w, tw, tg);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -201,85 +206,85 @@ __device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[16],
   }
 }
 
-template <class A, int LOGN2, int J, int ST>
-__device__ __forceinline__ void fwd_round_stages(const A& ar, typename A::V (&v)[16],
+template <class A, int LOGN2, int RB, int J, int ST>
+__device__ __forceinline__ void fwd_round_stages(const A& ar, typename A::V (&v)[1 << RB],
                                                  const typename A::TW* __restrict__ tw,
                                                  uint32_t base, uint32_t tt) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   if constexpr (ST < S::nst(J)) {
     constexpr int HB = S::hb(J);
-    constexpr int SP = 4 * J + ST;
+    constexpr int SP = RB * J + ST;
     constexpr int B = (LOGN2 - 1 - SP) - HB;
-    fwd_stage<A, B, SP, HB>(ar, v, tw, base, tt);
-    fwd_round_stages<A, LOGN2, J, ST + 1>(ar, v, tw, base, tt);
+    fwd_stage<A, RB, B, SP, HB>(ar, v, tw, base, tt);
+    fwd_round_stages<A, LOGN2, RB, J, ST + 1>(ar, v, tw, base, tt);
   }
 }
 
 // Inverse stages of round J run from the highest local stage down.
-template <class A, int LOGN2, int J, int ST, bool FOLD>
-__device__ __forceinline__ void inv_round_stages(const A& ar, typename A::V (&v)[16],
+template <class A, int LOGN2, int RB, int J, int ST, bool FOLD>
+__device__ __forceinline__ void inv_round_stages(const A& ar, typename A::V (&v)[1 << RB],
                                                  const typename A::TW* __restrict__ tw,
                                                  uint32_t base, uint32_t tt, const LimbDev& ld) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   if constexpr (ST < S::nst(J)) {
     constexpr int HB = S::hb(J);
-    constexpr int SP = 4 * J + S::nst(J) - 1 - ST;
+    constexpr int SP = RB * J + S::nst(J) - 1 - ST;
     constexpr int B = (LOGN2 - 1 - SP) - HB;
     if constexpr (FOLD && SP == 0) {
-      inv_stage<A, B, SP, HB, true>(ar, v, tw, base, tt, ld);
+      inv_stage<A, RB, B, SP, HB, true>(ar, v, tw, base, tt, ld);
     } else {
-      inv_stage<A, B, SP, HB, false>(ar, v, tw, base, tt, ld);
+      inv_stage<A, RB, B, SP, HB, false>(ar, v, tw, base, tt, ld);
     }
-    inv_round_stages<A, LOGN2, J, ST + 1, FOLD>(ar, v, tw, base, tt, ld);
+    inv_round_stages<A, LOGN2, RB, J, ST + 1, FOLD>(ar, v, tw, base, tt, ld);
   }
 }
 
-// Re-deal 16 values per thread from the layout of round JF to round JT.
-template <class A, int LOGN2, int JF, int JT>
-__device__ __forceinline__ void lds_exchange(typename A::V (&v)[16], typename A::V* lds,
+// Re-deal R values per thread from the layout of round JF to round JT.
+template <class A, int LOGN2, int RB, int JF, int JT>
+__device__ __forceinline__ void lds_exchange(typename A::V (&v)[1 << RB], typename A::V* lds,
                                              uint32_t tt) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   constexpr int HF = S::hb(JF), HT = S::hb(JT);
 #pragma unroll
-  for (int u = 0; u < 16; ++u) lds[lds_pad(ins_bits(tt, u, HF))] = v[u];
+  for (int u = 0; u < S::R; ++u) lds[lds_pad(ins_bits<RB>(tt, u, HF))] = v[u];
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < 16; ++u) v[u] = lds[lds_pad(ins_bits(tt, u, HT))];
+  for (int u = 0; u < S::R; ++u) v[u] = lds[lds_pad(ins_bits<RB>(tt, u, HT))];
   __syncthreads();
 }
 
-template <class A, int LOGN2, int J>
-__device__ __forceinline__ void row_forward_from(const A& ar, typename A::V (&v)[16],
+template <class A, int LOGN2, int RB, int J>
+__device__ __forceinline__ void row_forward_from(const A& ar, typename A::V (&v)[1 << RB],
                                                  const typename A::TW* __restrict__ tw,
                                                  uint32_t base, uint32_t tt, typename A::V* lds) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   if constexpr (J < S::K) {
-    fwd_round_stages<A, LOGN2, J, 0>(ar, v, tw, base, tt);
+    fwd_round_stages<A, LOGN2, RB, J, 0>(ar, v, tw, base, tt);
     if constexpr (J + 1 < S::K) {
       if constexpr (A::kCenterRounds) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) ar.center(v[u]);
+        for (int u = 0; u < S::R; ++u) ar.center(v[u]);
       }
-      lds_exchange<A, LOGN2, J, J + 1>(v, lds, tt);
-      row_forward_from<A, LOGN2, J + 1>(ar, v, tw, base, tt, lds);
+      lds_exchange<A, LOGN2, RB, J, J + 1>(v, lds, tt);
+      row_forward_from<A, LOGN2, RB, J + 1>(ar, v, tw, base, tt, lds);
     }
   }
 }
 
-template <class A, int LOGN2, int J, bool FOLD>
-__device__ __forceinline__ void row_inverse_from(const A& ar, typename A::V (&v)[16],
+template <class A, int LOGN2, int RB, int J, bool FOLD>
+__device__ __forceinline__ void row_inverse_from(const A& ar, typename A::V (&v)[1 << RB],
                                                  const typename A::TW* __restrict__ tw,
                                                  uint32_t base, uint32_t tt, typename A::V* lds,
                                                  const LimbDev& ld) {
   if constexpr (J >= 0) {
-    inv_round_stages<A, LOGN2, J, 0, FOLD>(ar, v, tw, base, tt, ld);
+    inv_round_stages<A, LOGN2, RB, J, 0, FOLD>(ar, v, tw, base, tt, ld);
     if constexpr (J > 0) {
       if constexpr (A::kCenterRounds) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) ar.center(v[u]);
+        for (int u = 0; u < (1 << RB); ++u) ar.center(v[u]);
       }
-      lds_exchange<A, LOGN2, J, J - 1>(v, lds, tt);
-      row_inverse_from<A, LOGN2, J - 1, FOLD>(ar, v, tw, base, tt, lds, ld);
+      lds_exchange<A, LOGN2, RB, J, J - 1>(v, lds, tt);
+      row_inverse_from<A, LOGN2, RB, J - 1, FOLD>(ar, v, tw, base, tt, lds, ld);
     }
   }
 }
@@ -323,40 +328,41 @@ __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int
 // ---------------------------------------------------------------------------
 // Row pass on one chunk of N2 = 2^LOGN2 words.  `dst`/`src` point at the
 // chunk, `base` = N1 + c is its twiddle base, `tt` the thread's index within
-// the chunk's N2/16 threads, `lds` the chunk's LDS region.  All threads of the
+// the chunk's N2/R threads (R = 2^RB values each), `lds` the chunk's LDS region.  All threads of the
 // workgroup must call it together (it synchronises the workgroup).
 // INV selects the direction; TWO_PASS says whether a column pass precedes
 // (forward) or follows (inverse): then the pass reads/writes the raw
 // intermediate format instead of canonical words, and the inverse leaves the
 // N^-1 scaling to the column pass.
-template <class A, int LOGN2, bool INV, bool TWO_PASS>
+template <class A, int LOGN2, bool INV, bool TWO_PASS, int RB = 4>
 __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
                                           const typename A::W* __restrict__ src, const LimbDev& ld,
                                           uint32_t base, uint32_t tt, typename A::V* lds,
                                           bool valid) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
+  constexpr int R = S::R;
   using V = typename A::V;
   using W = typename A::W;
   const A ar(ld);
-  V v[16];
+  V v[R];
   if constexpr (!INV) {
     constexpr int H0 = S::hb(0);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const W x = valid ? src[ins_bits(tt, u, H0)] : W(0);
+    for (int u = 0; u < R; ++u) {
+      const W x = valid ? src[ins_bits<RB>(tt, u, H0)] : W(0);
       v[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twf);
-    row_forward_from<A, LOGN2, 0>(ar, v, tw, base, tt, lds);
+    row_forward_from<A, LOGN2, RB, 0>(ar, v, tw, base, tt, lds);
     if constexpr (S::K > 1) {
-      // The last round holds 16 consecutive words per thread; re-deal them
+      // The last round holds R consecutive words per thread; re-deal them
       // through LDS so that each store instruction writes contiguous words.
 #pragma unroll
-      for (int u = 0; u < 16; ++u) lds[lds_pad((tt << 4) | u)] = v[u];
+      for (int u = 0; u < R; ++u) lds[lds_pad((tt << RB) | u)] = v[u];
       __syncthreads();
       if (valid) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < R; ++u) {
           const uint32_t y = tt + u * S::TPC;
           dst[y] = ar.to_word(lds[lds_pad(y)]);
         }
@@ -364,13 +370,13 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
       __syncthreads();
     } else if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) dst[u] = ar.to_word(v[u]);
+      for (int u = 0; u < R; ++u) dst[u] = ar.to_word(v[u]);
     }
   } else {
     if constexpr (S::K > 1) {
-      // Contiguous loads into LDS, then each thread takes 16 consecutive words.
+      // Contiguous loads into LDS, then each thread takes R consecutive words.
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < R; ++u) {
         const uint32_t y = tt + u * S::TPC;
         const W x = valid ? src[y] : W(0);
         V t = ar.from_word(x);
@@ -379,38 +385,40 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
       }
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = lds[lds_pad((tt << 4) | u)];
+      for (int u = 0; u < R; ++u) v[u] = lds[lds_pad((tt << RB) | u)];
       __syncthreads();
     } else {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < R; ++u) {
         const W x = valid ? src[u] : W(0);
         v[u] = ar.from_word(x);
         ar.center(v[u]);
       }
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twi);
-    row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, v, tw, base, tt, lds, ld);
+    row_inverse_from<A, LOGN2, RB, S::K - 1, !TWO_PASS>(ar, v, tw, base, tt, lds, ld);
     constexpr int H0 = S::hb(0);
     if (valid) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        dst[ins_bits(tt, u, H0)] = TWO_PASS ? ar.to_raw(v[u]) : ar.to_word(v[u]);
+      for (int u = 0; u < R; ++u)
+        dst[ins_bits<RB>(tt, u, H0)] = TWO_PASS ? ar.to_raw(v[u]) : ar.to_word(v[u]);
     }
   }
 }
 
-template <class A, int LOGN2, bool INV, bool TWO_PASS>
-__global__ void __launch_bounds__(RowShape<LOGN2>::BLOCK)
+// Radix-16 rows: ask for four waves per SIMD (<= 128 VGPRs); the LDS of four
+// workgroups per CU allows no more anyway.
+template <class A, int LOGN2, bool INV, bool TWO_PASS, int RB = 4>
+__global__ void __launch_bounds__((RowShape<LOGN2, RB>::BLOCK), (RB == 4 ? 4 : 1))
 row_kernel(RowArgs args) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   using V = typename A::V;
   using W = typename A::W;
   __shared__ V lds_all[S::LDS_ELEMS];
   const uint32_t ci = threadIdx.x / S::TPC;
   const uint32_t tt = threadIdx.x & (S::TPC - 1);
   const ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
-  row_chunk<A, LOGN2, INV, TWO_PASS>(reinterpret_cast<W*>(args.dst) + cp.off,
+  row_chunk<A, LOGN2, INV, TWO_PASS, RB>(reinterpret_cast<W*>(args.dst) + cp.off,
                                      reinterpret_cast<const W*>(args.src) + cp.off,
                                      args.limbs[cp.limb], cp.base, tt,
                                      lds_all + ci * S::CHUNK_LDS, cp.valid);
@@ -420,10 +428,11 @@ row_kernel(RowArgs args) {
 // product, inverse -- Eq. (1) without leaving registers/LDS.  With TWO_PASS
 // the inputs are column-pass outputs and the result still needs the inverse
 // column pass.
-template <class A, int LOGN2, bool TWO_PASS>
-__global__ void __launch_bounds__(RowShape<LOGN2>::BLOCK)
+template <class A, int LOGN2, bool TWO_PASS, int RB = 4>
+__global__ void __launch_bounds__((RowShape<LOGN2, RB>::BLOCK))
 polymul_row_kernel(RowArgs args) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
+  constexpr int R = S::R;
   using V = typename A::V;
   using W = typename A::W;
   __shared__ V lds_all[S::LDS_ELEMS];
@@ -439,29 +448,29 @@ polymul_row_kernel(RowArgs args) {
   const auto* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
   const auto* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
   constexpr int H0 = S::hb(0);
-  V va[16], vb[16];
+  V va[R], vb[R];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const W x = cp.valid ? sa[ins_bits(tt, u, H0)] : W(0);
+  for (int u = 0; u < R; ++u) {
+    const W x = cp.valid ? sa[ins_bits<RB>(tt, u, H0)] : W(0);
     va[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
   }
-  row_forward_from<A, LOGN2, 0>(ar, va, twf, cp.base, tt, lds);
+  row_forward_from<A, LOGN2, RB, 0>(ar, va, twf, cp.base, tt, lds);
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const W x = cp.valid ? sb[ins_bits(tt, u, H0)] : W(0);
+  for (int u = 0; u < R; ++u) {
+    const W x = cp.valid ? sb[ins_bits<RB>(tt, u, H0)] : W(0);
     vb[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
   }
-  row_forward_from<A, LOGN2, 0>(ar, vb, twf, cp.base, tt, lds);
+  row_forward_from<A, LOGN2, RB, 0>(ar, vb, twf, cp.base, tt, lds);
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
+  for (int u = 0; u < R; ++u) {
     va[u] = ar.mul(va[u], vb[u]);
     ar.center(va[u]);
   }
-  row_inverse_from<A, LOGN2, S::K - 1, !TWO_PASS>(ar, va, twi, cp.base, tt, lds, ld);
+  row_inverse_from<A, LOGN2, RB, S::K - 1, !TWO_PASS>(ar, va, twi, cp.base, tt, lds, ld);
   if (cp.valid) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      dst[ins_bits(tt, u, H0)] = TWO_PASS ? ar.to_raw(va[u]) : ar.to_word(va[u]);
+    for (int u = 0; u < R; ++u)
+      dst[ins_bits<RB>(tt, u, H0)] = TWO_PASS ? ar.to_raw(va[u]) : ar.to_word(va[u]);
   }
 }
 

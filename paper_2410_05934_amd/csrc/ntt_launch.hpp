@@ -13,21 +13,22 @@ namespace nttk {
 // ---------------------------------------------------------------------------
 // Launchers
 
-template <class A, int LOGN2, bool INV, bool TWO>
+template <class A, int LOGN2, bool INV, bool TWO, int RB = 4>
 hipError_t launch_row_n(const RowArgs& a, hipStream_t s) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
-  LaunchTimer t("row", A::kName, LOGN2, INV, TWO, (uint64_t)a.total_chunks << LOGN2, s);
-  hipLaunchKernelGGL((row_kernel<A, LOGN2, INV, TWO>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
+  LaunchTimer t(RB == 4 ? "row" : "row8", A::kName, LOGN2, INV, TWO, (uint64_t)a.total_chunks << LOGN2, s);
+  hipLaunchKernelGGL((row_kernel<A, LOGN2, INV, TWO, RB>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
-template <class A, int LOGN2, bool TWO>
+template <class A, int LOGN2, bool TWO, int RB = 4>
 hipError_t launch_pm_n(const RowArgs& a, hipStream_t s) {
-  using S = RowShape<LOGN2>;
+  using S = RowShape<LOGN2, RB>;
   const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
-  LaunchTimer t("polymul_row", A::kName, LOGN2, false, TWO, (uint64_t)a.total_chunks << LOGN2, s);
-  hipLaunchKernelGGL((polymul_row_kernel<A, LOGN2, TWO>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
+  LaunchTimer t(RB == 4 ? "polymul_row" : "polymul_row8", A::kName, LOGN2, false, TWO,
+                (uint64_t)a.total_chunks << LOGN2, s);
+  hipLaunchKernelGGL((polymul_row_kernel<A, LOGN2, TWO, RB>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
   return hipGetLastError();
 }
 
@@ -40,7 +41,16 @@ hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
 }
 
 template <class A, bool INV, bool TWO>
-hipError_t launch_row(int logn2, const RowArgs& a, hipStream_t s) {
+hipError_t launch_row(int logn2, const RowArgs& a, hipStream_t s, int rb = 4) {
+  if (rb == 3) {
+    switch (logn2) {
+      case 10: return launch_row_n<A, 10, INV, TWO, 3>(a, s);
+      case 11: return launch_row_n<A, 11, INV, TWO, 3>(a, s);
+      case 12: return launch_row_n<A, 12, INV, TWO, 3>(a, s);
+      case 13: return launch_row_n<A, 13, INV, TWO, 3>(a, s);
+      default: break;
+    }
+  }
   switch (logn2) {
     case 4: return launch_row_n<A, 4, INV, TWO>(a, s);
     case 5: return launch_row_n<A, 5, INV, TWO>(a, s);
@@ -58,7 +68,16 @@ hipError_t launch_row(int logn2, const RowArgs& a, hipStream_t s) {
 }
 
 template <class A, bool TWO>
-hipError_t launch_pm(int logn2, const RowArgs& a, hipStream_t s) {
+hipError_t launch_pm(int logn2, const RowArgs& a, hipStream_t s, int rb = 4) {
+  if (rb == 3) {
+    switch (logn2) {
+      case 10: return launch_pm_n<A, 10, TWO, 3>(a, s);
+      case 11: return launch_pm_n<A, 11, TWO, 3>(a, s);
+      case 12: return launch_pm_n<A, 12, TWO, 3>(a, s);
+      case 13: return launch_pm_n<A, 13, TWO, 3>(a, s);
+      default: break;
+    }
+  }
   switch (logn2) {
     case 4: return launch_pm_n<A, 4, TWO>(a, s);
     case 5: return launch_pm_n<A, 5, TWO>(a, s);
@@ -124,10 +143,11 @@ template <class A>
 hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
                          uint32_t split, hipStream_t s) {
   const int n = p->log_n, n1 = (int)split, n2 = n - n1;
+  const int rb = row_rb_for(p, inv, split, batch);
   hipError_t e = hipSuccess;
   if (n1 == 0) {
     RowArgs a = row_args(p, c, data, data, nullptr, batch, n1);
-    e = inv ? launch_row<A, true, false>(n2, a, s) : launch_row<A, false, false>(n2, a, s);
+    e = inv ? launch_row<A, true, false>(n2, a, s, rb) : launch_row<A, false, false>(n2, a, s, rb);
   } else if (n2 == 0) {
     ColArgs a = col_args(p, c, data, data, batch, n1);
     e = inv ? launch_col<A, true, false>(n1, a, s) : launch_col<A, false, false>(n1, a, s);
@@ -136,11 +156,11 @@ hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch,
     e = launch_col<A, false, true>(n1, ca, s);
     if (e == hipSuccess) {
       RowArgs ra = row_args(p, c, data, data, nullptr, batch, n1);
-      e = launch_row<A, false, true>(n2, ra, s);
+      e = launch_row<A, false, true>(n2, ra, s, rb);
     }
   } else {
     RowArgs ra = row_args(p, c, data, data, nullptr, batch, n1);
-    e = launch_row<A, true, true>(n2, ra, s);
+    e = launch_row<A, true, true>(n2, ra, s, rb);
     if (e == hipSuccess) {
       ColArgs ca = col_args(p, c, data, data, batch, n1);
       e = launch_col<A, true, true>(n1, ca, s);
@@ -173,10 +193,11 @@ template <class A>
 hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
                        void* ws, uint32_t batch, uint32_t split, hipStream_t s) {
   const int n = p->log_n, n1 = (int)split, n2 = n - n1;
+  const int rb = p->row_rb ? p->row_rb : 4;
   hipError_t e;
   if (n1 == 0) {
     RowArgs ra = row_args(p, c, out, a, b, batch, n1);
-    return launch_pm<A, false>(n2, ra, s);
+    return launch_pm<A, false>(n2, ra, s, rb);
   }
   if (n2 == 0) {
     // Tiny N: forward both into out / ws, multiply, inverse.
@@ -193,7 +214,7 @@ hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, con
   ca = col_args(p, c, ws, b, batch, n1);
   if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
   RowArgs ra = row_args(p, c, out, out, ws, batch, n1);
-  if ((e = launch_pm<A, true>(n2, ra, s)) != hipSuccess) return e;
+  if ((e = launch_pm<A, true>(n2, ra, s, rb)) != hipSuccess) return e;
   ca = col_args(p, c, out, out, batch, n1);
   return launch_col<A, true, true>(n1, ca, s);
 }

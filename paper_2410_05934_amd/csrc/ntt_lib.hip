@@ -259,6 +259,7 @@ ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* moduli,
   p->flags = flags;
   p->log_n1 = n1;
   p->forced_split = (flags & NTT_FLAG_SPLIT_MASK) ? (int)n1 : -1;
+  p->row_rb = (flags & NTT_FLAG_ROW_RADIX8) ? 3 : 0;
   p->moduli.assign(moduli, moduli + num_moduli);
   p->psi.resize(num_moduli);
   p->cls.resize(num_moduli);

@@ -7,8 +7,10 @@
 // batch * L * N1 chunks and the best split moves with the batch.  The tuner
 // therefore measures: for a shape it times every admissible split on scratch
 // data and records the fastest under the key (log2 N, arithmetic class,
-// floor(log2(batch * L))).  Calls without a forced split look the key up (the
-// nearest recorded row bucket within two powers of two), else use the default.
+// floor(log2(batch * L))).  With each split it also times both row-pass
+// radices (16 or 8 values per thread) per direction and records the faster.
+// Calls without a forced split look the keys up (the nearest recorded row
+// bucket within two powers of two), else use the defaults.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,7 +35,8 @@ struct Entry {
   float us;
 };
 
-// key: (kind, log_n, cls, bucket); kind 0 = pass split, 1 = ragged row length
+// key: (kind, log_n, cls, bucket); kind 0 = pass split, 1 = ragged row length,
+// 2 / 3 = values per thread (log2) of forward / inverse row passes
 using Key = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
 
 std::mutex g_mu;
@@ -118,6 +121,23 @@ uint32_t tuned_split_for(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t f
   return fallback;
 }
 
+uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  ensure_env_loaded();
+  const uint32_t b = bucket_of(rows);
+  for (int d = 0; d <= 2; ++d) {
+    for (int sgn : {1, -1}) {
+      const int bb = (int)b + sgn * d;
+      if (bb < 0) continue;
+      auto it = g_table.find(Key(kind, log_n, cls, (uint32_t)bb));
+      if (it != g_table.end() && (it->second.value == 3 || it->second.value == 4))
+        return it->second.value;
+      if (d == 0) break;
+    }
+  }
+  return fallback;
+}
+
 uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback) {
   std::lock_guard<std::mutex> lk(g_mu);
   ensure_env_loaded();
@@ -157,37 +177,49 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
   const int reps = (int)std::max<uint64_t>(3, std::min<uint64_t>(40, (1ull << 24) / std::max<uint64_t>(1, words)));
+  // Time one direction of one (split, radix) configuration.
+  auto time_dir = [&](ntt_plan_t p, bool inv, float* us) -> ntt_status {
+    for (int w = 0; w < 2; ++w) (inv ? ntt_inverse : ntt_forward)(p, buf, batch, s);
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < reps; ++r) (inv ? ntt_inverse : ntt_forward)(p, buf, batch, s);
+    (void)hipEventRecord(b, s);
+    hipError_t he = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, a, b);
+    if (he != hipSuccess) return hip_fail(he, "tuning run");
+    *us = ms * 1000.f / reps;
+    return NTT_OK;
+  };
   float best = 1e30f;
-  uint32_t best_split = 0;
+  uint32_t best_split = 0, best_rb_f = 4, best_rb_i = 4;
   ntt_status st = NTT_OK;
   bool any = false;
-  for (int n1 = 0; n1 <= log_n; ++n1) {
+  for (int n1 = 0; n1 <= log_n && st == NTT_OK; ++n1) {
     if (!split_valid(log_n, n1)) continue;
-    ntt_plan_t p = nullptr;
-    st = ntt_plan_create(&p, N, moduli, num_moduli, word_bits, NTT_FLAG_SPLIT(n1));
+    const int n2 = log_n - n1;
+    float bf = 1e30f, bi = 1e30f;
+    uint32_t rf = 4, ri = 4;
+    for (int rb : {4, 3}) {
+      if (rb == 3 && (n2 < 10 || n2 > 13)) continue;
+      ntt_plan_t p = nullptr;
+      st = ntt_plan_create(&p, N, moduli, num_moduli, word_bits,
+                           NTT_FLAG_SPLIT(n1) | (rb == 3 ? NTT_FLAG_ROW_RADIX8 : 0u));
+      if (st != NTT_OK) break;
+      if (rb == 4) p->row_rb = 4;  // pin radix-16 for this measurement
+      float uf = 0, ui = 0;
+      st = time_dir(p, false, &uf);
+      if (st == NTT_OK) st = time_dir(p, true, &ui);
+      ntt_plan_destroy(p);
+      if (st != NTT_OK) break;
+      if (uf < bf) { bf = uf; rf = (uint32_t)rb; }
+      if (ui < bi) { bi = ui; ri = (uint32_t)rb; }
+    }
     if (st != NTT_OK) break;
-    for (int w = 0; w < 2; ++w) {
-      ntt_forward(p, buf, batch, s);
-      ntt_inverse(p, buf, batch, s);
-    }
-    (void)hipEventRecord(a, s);
-    for (int r = 0; r < reps; ++r) {
-      ntt_forward(p, buf, batch, s);
-      ntt_inverse(p, buf, batch, s);
-    }
-    (void)hipEventRecord(b, s);
-    e = hipEventSynchronize(b);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-    ntt_plan_destroy(p);
-    if (e != hipSuccess) {
-      st = hip_fail(e, "tuning run");
-      break;
-    }
-    const float us = ms * 1000.f / reps;
-    if (us < best) {
-      best = us;
+    if (bf + bi < best) {
+      best = bf + bi;
       best_split = (uint32_t)n1;
+      best_rb_f = rf;
+      best_rb_i = ri;
     }
     any = true;
   }
@@ -200,8 +232,11 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
   {
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_env_loaded();
-    g_table[Key(0u, (uint32_t)log_n, class_of(moduli[0], word_bits),
-                bucket_of((uint64_t)batch * num_moduli))] = Entry{best_split, best};
+    const uint32_t cls = class_of(moduli[0], word_bits);
+    const uint32_t bk = bucket_of((uint64_t)batch * num_moduli);
+    g_table[Key(0u, (uint32_t)log_n, cls, bk)] = Entry{best_split, best};
+    g_table[Key(2u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_f, 0.f};
+    g_table[Key(3u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_i, 0.f};
   }
   if (best_n1) *best_n1 = best_split;
   if (best_us) *best_us = best;

@@ -237,3 +237,21 @@ def test_repeat_runs_are_identical():
     r1 = _run_fwd(plan, a, 64)
     r2 = _run_fwd(plan, a, 64)
     assert np.array_equal(r1, r2)
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+@pytest.mark.parametrize("logn", [10, 12, 13, 15, 16])
+def test_radix8_rows_are_bit_identical(cls, logn):
+    """Row passes with 8 values per thread (radix-8 rounds) give the same words."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    a = _data(77 + logn, moduli, 3, N, word_bits)
+    b = _data(78 + logn, moduli, 3, N, word_bits)
+    plan = ntt.Plan(N, moduli, word_bits, flags=ntt.FLAG_ROW_RADIX8)
+    assert np.array_equal(_run_fwd(plan, a, word_bits), oracle.forward(a, moduli))
+    assert np.array_equal(_run_inv(plan, a, word_bits), oracle.inverse(a, moduli))
+    da, db = to_device(a, word_bits), to_device(b, word_bits)
+    out = empty_device(a.shape, word_bits)
+    plan.polymul(out, da, db)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
