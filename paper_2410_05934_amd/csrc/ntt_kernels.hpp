@@ -91,6 +91,10 @@ struct MacArgs {
   uint64_t total;            // groups * n_cls * N
 };
 
+// Padded LDS index: one spare slot after every 16 (spreads strided accesses
+// over the banks).
+__device__ __forceinline__ uint32_t lds_pad(uint32_t y) { return y + (y >> 4); }
+
 // Row-chunk geometry: 2^LOGN2 words, R = 2^RB values per thread (radix-R
 // rounds of RB fused stages).
 template <int LOGN2, int RB = 4>
@@ -103,6 +107,11 @@ struct RowShape {
   static constexpr int K = (LOGN2 + RB - 1) / RB;  // rounds
   static constexpr int LAST = LOGN2 - RB * (K - 1);  // stages in the last round
   static constexpr int CHUNK_LDS = K > 1 ? N2 + N2 / 16 : 1;
+  // slot of word tt + u*TPC in the padded chunk (linear in u when TPC % 16 == 0)
+  __device__ __forceinline__ static uint32_t tail_slot(uint32_t tt, uint32_t u) {
+    if constexpr (TPC % 16 == 0) return lds_pad(tt) + u * (TPC + TPC / 16);
+    else return lds_pad(tt + u * TPC);
+  }
   static constexpr int LDS_ELEMS = CPW * CHUNK_LDS;
   // held-bit offset of round j (forward numbering)
   static constexpr int hb(int j) { return j < K - 1 ? LOGN2 - RB - RB * j : 0; }
@@ -123,7 +132,24 @@ template <int RB = 4>
 __device__ __forceinline__ uint32_t ins_bits(uint32_t tt, uint32_t u, int hb) {
   return ((tt >> hb) << (hb + RB)) | (u << hb) | (tt & ((1u << hb) - 1u));
 }
-__device__ __forceinline__ uint32_t lds_pad(uint32_t y) { return y + (y >> 4); }
+
+// Padded LDS slot of value u of thread tt in a round holding RB bits at HB.
+// When the value bits sit at or above bit 4 (HB >= 4), or at the bottom with
+// RB <= 4 (HB == 0), the slot is base(tt) + u * STRIDE with a compile-time
+// stride, which the compiler folds into the ds instruction's offset field;
+// otherwise it is computed per value.
+template <int RB, int HB>
+struct LdsMap {
+  static constexpr bool kLinear = HB >= 4 || HB == 0;
+  static constexpr uint32_t kStride = HB >= 4 ? ((1u << HB) + (1u << (HB - 4))) : 1u;
+  __device__ __forceinline__ static uint32_t base(uint32_t tt) {
+    return lds_pad(ins_bits<RB>(tt, 0, HB));
+  }
+  __device__ __forceinline__ static uint32_t slot(uint32_t tt, uint32_t bse, uint32_t u) {
+    if constexpr (kLinear) return bse + u * kStride;
+    else return lds_pad(ins_bits<RB>(tt, u, HB));
+  }
+};
 
 // One table entry from global memory (fp64 entry or Shoup pair).
 template <class TW>
@@ -245,11 +271,14 @@ __device__ __forceinline__ void lds_exchange(typename A::V (&v)[1 << RB], typena
                                              uint32_t tt) {
   using S = RowShape<LOGN2, RB>;
   constexpr int HF = S::hb(JF), HT = S::hb(JT);
+  using MF = LdsMap<RB, HF>;
+  using MT = LdsMap<RB, HT>;
+  const uint32_t bf = MF::base(tt), bt = MT::base(tt);
 #pragma unroll
-  for (int u = 0; u < S::R; ++u) lds[lds_pad(ins_bits<RB>(tt, u, HF))] = v[u];
+  for (int u = 0; u < S::R; ++u) lds[MF::slot(tt, bf, u)] = v[u];
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < S::R; ++u) v[u] = lds[lds_pad(ins_bits<RB>(tt, u, HT))];
+  for (int u = 0; u < S::R; ++u) v[u] = lds[MT::slot(tt, bt, u)];
   __syncthreads();
 }
 
@@ -327,6 +356,8 @@ __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int
 
 // ---------------------------------------------------------------------------
 // Row pass on one chunk of N2 = 2^LOGN2 words.  `dst`/`src` point at the
+// chunk (always a readable chunk: threads without a chunk of their own pass
+// chunk 0 and valid = false, so loads need no guard; only stores are skipped).
 // chunk, `base` = N1 + c is its twiddle base, `tt` the thread's index within
 // the chunk's N2/R threads (R = 2^RB values each), `lds` the chunk's LDS region.  All threads of the
 // workgroup must call it together (it synchronises the workgroup).
@@ -349,7 +380,7 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
     constexpr int H0 = S::hb(0);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const W x = valid ? src[ins_bits<RB>(tt, u, H0)] : W(0);
+      const W x = src[ins_bits<RB>(tt, u, H0)];
       v[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
     }
     const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twf);
@@ -357,15 +388,14 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
     if constexpr (S::K > 1) {
       // The last round holds R consecutive words per thread; re-deal them
       // through LDS so that each store instruction writes contiguous words.
+      using MB = LdsMap<RB, 0>;
+      const uint32_t bb = MB::base(tt);
 #pragma unroll
-      for (int u = 0; u < R; ++u) lds[lds_pad((tt << RB) | u)] = v[u];
+      for (int u = 0; u < R; ++u) lds[MB::slot(tt, bb, u)] = v[u];
       __syncthreads();
       if (valid) {
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const uint32_t y = tt + u * S::TPC;
-          dst[y] = ar.to_word(lds[lds_pad(y)]);
-        }
+        for (int u = 0; u < R; ++u) dst[tt + u * S::TPC] = ar.to_word(lds[S::tail_slot(tt, u)]);
       }
       __syncthreads();
     } else if (valid) {
@@ -377,20 +407,21 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
       // Contiguous loads into LDS, then each thread takes R consecutive words.
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const uint32_t y = tt + u * S::TPC;
-        const W x = valid ? src[y] : W(0);
+        const W x = src[tt + u * S::TPC];
         V t = ar.from_word(x);
         ar.center(t);
-        lds[lds_pad(y)] = t;
+        lds[S::tail_slot(tt, u)] = t;
       }
       __syncthreads();
+      using MB = LdsMap<RB, 0>;
+      const uint32_t bb = MB::base(tt);
 #pragma unroll
-      for (int u = 0; u < R; ++u) v[u] = lds[lds_pad((tt << RB) | u)];
+      for (int u = 0; u < R; ++u) v[u] = lds[MB::slot(tt, bb, u)];
       __syncthreads();
     } else {
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const W x = valid ? src[u] : W(0);
+        const W x = src[u];
         v[u] = ar.from_word(x);
         ar.center(v[u]);
       }
@@ -451,13 +482,13 @@ polymul_row_kernel(RowArgs args) {
   V va[R], vb[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const W x = cp.valid ? sa[ins_bits<RB>(tt, u, H0)] : W(0);
+    const W x = sa[ins_bits<RB>(tt, u, H0)];
     va[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
   }
   row_forward_from<A, LOGN2, RB, 0>(ar, va, twf, cp.base, tt, lds);
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const W x = cp.valid ? sb[ins_bits<RB>(tt, u, H0)] : W(0);
+    const W x = sb[ins_bits<RB>(tt, u, H0)];
     vb[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
   }
   row_forward_from<A, LOGN2, RB, 0>(ar, vb, twf, cp.base, tt, lds);
@@ -494,7 +525,7 @@ __device__ __forceinline__ void col_one(typename A::W* __restrict__ dst,
     const NTT_GLOBAL TW* tw = gptr(reinterpret_cast<const TW*>(ld.twf));
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const W x = valid ? src[(uint64_t)k << log_n2] : W(0);
+      const W x = src[(uint64_t)k << log_n2];
       v[k] = ar.from_word(x);
     }
 #pragma unroll
@@ -522,7 +553,7 @@ __device__ __forceinline__ void col_one(typename A::W* __restrict__ dst,
     const NTT_GLOBAL TW* tw = gptr(reinterpret_cast<const TW*>(ld.twi));
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      const W x = valid ? src[(uint64_t)k << log_n2] : W(0);
+      const W x = src[(uint64_t)k << log_n2];
       v[k] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
       ar.center(v[k]);
     }
