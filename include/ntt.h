@@ -68,7 +68,9 @@ typedef enum {
  * exact fp64 arithmetic would be chosen (testing and measurement). */
 #define NTT_FLAG_FORCE_INT64 (1u << 16)
 /* Row passes of 2^10 .. 2^13 words with 8 values per thread (radix-8 rounds,
- * twice the threads of the default radix-16 rounds, one more LDS exchange). */
+ * twice the threads of radix-16 rounds, one more LDS exchange).  Without it the
+ * tuning table chooses per direction and shape, else radix-8 for inverse and
+ * polymul rows and radix-16 for forward rows. */
 #define NTT_FLAG_ROW_RADIX8 (1u << 17)
 
 /* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
@@ -259,7 +261,10 @@ ntt_status ntt_server_destroy(ntt_server_t s);
  * Later calls with a similar number of limb-rows (same power-of-two bucket of
  * batch * L) and no forced split use it.  The paper's switch trigger (chunks
  * closest to the SM count, Sec. V-D) is for one polynomial; a batch changes the
- * concurrency, so the split is measured per (N, class, rows). */
+ * concurrency, so the split is measured per (N, class, rows).  Each split is
+ * timed with 16 and with 8 values per row-pass thread and the faster is kept
+ * per direction; polymul rows at the chosen split are timed the same way when
+ * a second scratch buffer of the same size can be allocated. */
 ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_moduli,
                           uint32_t word_bits, uint32_t batch, uint32_t* best_n1, float* best_us);
 

@@ -84,8 +84,8 @@ uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback);
 bool split_valid(int log_n, int n1);
 
 // Values per thread (log2) of row passes: forced by NTT_FLAG_ROW_RADIX8, else the
-// tuning table, else radix-8 for inverse rows of 2^10..2^13 words (more waves to
-// hide the inverse's early loads) and radix-16 for forward and polymul rows.
+// tuning table, else radix-8 for inverse and polymul rows of 2^10..2^13 words (more
+// waves to hide their early loads) and radix-16 for forward rows.
 uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback);
 inline int dominant_class(const ntt_plan_s* p) {
   uint32_t best = 0, cnt = 0;
@@ -100,6 +100,13 @@ inline int row_rb_for(const ntt_plan_s* p, bool inv, uint32_t split, uint32_t ba
   const uint32_t fallback = inv ? 3u : 4u;
   return (int)tuned_row_rb(inv ? 3u : 2u, p->log_n, (uint32_t)dominant_class(p),
                            (uint64_t)batch * p->L, fallback);
+}
+
+inline int polymul_rb_for(const ntt_plan_s* p, uint32_t split, uint32_t batch) {
+  const int n2 = (int)p->log_n - (int)split;
+  if (n2 < 10 || n2 > 13) return 4;
+  if (p->row_rb) return p->row_rb;
+  return (int)tuned_row_rb(4u, p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L, 3u);
 }
 
 // Split used by one call over `batch` polynomials.

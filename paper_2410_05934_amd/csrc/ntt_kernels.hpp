@@ -356,11 +356,12 @@ __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int
 
 // ---------------------------------------------------------------------------
 // Row pass on one chunk of N2 = 2^LOGN2 words.  `dst`/`src` point at the
-// chunk (always a readable chunk: threads without a chunk of their own pass
-// chunk 0 and valid = false, so loads need no guard; only stores are skipped).
-// chunk, `base` = N1 + c is its twiddle base, `tt` the thread's index within
-// the chunk's N2/R threads (R = 2^RB values each), `lds` the chunk's LDS region.  All threads of the
-// workgroup must call it together (it synchronises the workgroup).
+// chunk (always a readable one: threads without a chunk of their own pass
+// chunk 0 and valid = false, so loads need no guard and only stores are
+// skipped); `base` = N1 + c is its twiddle base, `tt` the thread's index within
+// the chunk's N2/R threads (R = 2^RB values each), `lds` the chunk's LDS
+// region.  All threads of the workgroup must call it together (it
+// synchronises the workgroup).
 // INV selects the direction; TWO_PASS says whether a column pass precedes
 // (forward) or follows (inverse): then the pass reads/writes the raw
 // intermediate format instead of canonical words, and the inverse leaves the

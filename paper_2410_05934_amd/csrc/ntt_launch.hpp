@@ -193,7 +193,7 @@ template <class A>
 hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
                        void* ws, uint32_t batch, uint32_t split, hipStream_t s) {
   const int n = p->log_n, n1 = (int)split, n2 = n - n1;
-  const int rb = p->row_rb ? p->row_rb : 4;
+  const int rb = polymul_rb_for(p, split, batch);
   hipError_t e;
   if (n1 == 0) {
     RowArgs ra = row_args(p, c, out, a, b, batch, n1);

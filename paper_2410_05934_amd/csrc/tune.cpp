@@ -36,7 +36,7 @@ struct Entry {
 };
 
 // key: (kind, log_n, cls, bucket); kind 0 = pass split, 1 = ragged row length,
-// 2 / 3 = values per thread (log2) of forward / inverse row passes
+// 2 / 3 / 4 = values per thread (log2) of forward / inverse / polymul row passes
 using Key = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
 
 std::mutex g_mu;
@@ -223,6 +223,39 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
     }
     any = true;
   }
+  // Polymul rows at the chosen split: radix-16 against radix-8 (b aliases a; out
+  // is a second buffer).  Skipped when that buffer cannot be had.
+  uint32_t best_rb_pm = 0;
+  if (st == NTT_OK && any) {
+    // polymul's own split rule: a single-pass 2^14 polymul runs two-pass
+    const uint32_t pm_split = (best_split == 0 && log_n == 14) ? 1u : best_split;
+    const int n2 = log_n - (int)pm_split;
+    void* out = nullptr;
+    if (n2 >= 10 && n2 <= 13 && hipMalloc(&out, bytes) == hipSuccess) {
+      float bp = 1e30f;
+      for (int rb : {4, 3}) {
+        ntt_plan_t p = nullptr;
+        st = ntt_plan_create(&p, N, moduli, num_moduli, word_bits,
+                             NTT_FLAG_SPLIT(best_split) | (rb == 3 ? NTT_FLAG_ROW_RADIX8 : 0u));
+        if (st != NTT_OK) break;
+        if (rb == 4) p->row_rb = 4;
+        for (int w = 0; w < 2 && st == NTT_OK; ++w) st = ntt_polymul(p, out, buf, buf, batch, s);
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < reps && st == NTT_OK; ++r) st = ntt_polymul(p, out, buf, buf, batch, s);
+        (void)hipEventRecord(b, s);
+        hipError_t he = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, a, b);
+        ntt_plan_destroy(p);
+        if (st != NTT_OK) break;
+        if (he != hipSuccess) { st = hip_fail(he, "tuning run"); break; }
+        if (ms < bp) { bp = ms; best_rb_pm = (uint32_t)rb; }
+      }
+      (void)hipFree(out);
+    } else {
+      (void)hipGetLastError();
+    }
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   (void)hipStreamDestroy(s);
@@ -237,6 +270,7 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
     g_table[Key(0u, (uint32_t)log_n, cls, bk)] = Entry{best_split, best};
     g_table[Key(2u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_f, 0.f};
     g_table[Key(3u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_i, 0.f};
+    if (best_rb_pm) g_table[Key(4u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_pm, 0.f};
   }
   if (best_n1) *best_n1 = best_split;
   if (best_us) *best_us = best;

@@ -255,3 +255,32 @@ def test_radix8_rows_are_bit_identical(cls, logn):
     plan.polymul(out, da, db)
     torch.cuda.synchronize()
     assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+@pytest.mark.parametrize("logn", [10, 13, 16])
+def test_tuning_table_radix16_rows_are_bit_identical(cls, logn, tmp_path):
+    """A tuning table that picks 16 values per row-pass thread for every direction
+    (forward, inverse and polymul rows) gives the same words as the oracle."""
+    import json
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    entries = [{"kind": k, "log_n": logn, "cls": c, "bucket": b, "value": 4}
+               for k in (2, 3, 4) for c in range(3) for b in range(25)]
+    path = tmp_path / "rb16.json"
+    path.write_text(json.dumps({"entries": entries}))
+    ntt.tune_clear()
+    ntt.tune_load(str(path))
+    try:
+        a = _data(91 + logn, moduli, 3, N, word_bits)
+        b = _data(92 + logn, moduli, 3, N, word_bits)
+        plan = ntt.Plan(N, moduli, word_bits)
+        assert np.array_equal(_run_fwd(plan, a, word_bits), oracle.forward(a, moduli))
+        assert np.array_equal(_run_inv(plan, a, word_bits), oracle.inverse(a, moduli))
+        da, db = to_device(a, word_bits), to_device(b, word_bits)
+        out = empty_device(a.shape, word_bits)
+        plan.polymul(out, da, db)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
+    finally:
+        ntt.tune_clear()
