@@ -72,6 +72,12 @@ typedef enum {
  * tuning table chooses per direction and shape, else radix-8 for inverse and
  * polymul rows and radix-16 for forward rows. */
 #define NTT_FLAG_ROW_RADIX8 (1u << 17)
+/* Two-pass transforms with 2^12-word rows (N = 2^13 .. 2^16) run both passes in
+ * one persistent launch: the one global synchronisation per transform of the
+ * paper's single-kernel hybrid NTT (Sec. V-D) becomes a per-transform counter
+ * that row (forward) or column (inverse) pieces wait on.  Results are
+ * bit-identical to the two-launch form. */
+#define NTT_FLAG_FUSED (1u << 18)
 
 /* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
  * precomputed per modulus as the paper keeps them in constant memory, Sec. II-E).

@@ -3,7 +3,7 @@
 
 namespace nttk {
 template hipError_t transform_cls<ArF64S>(const ntt_plan_s*, int, void*, uint32_t, bool,
-                                         uint32_t, hipStream_t);
+                                        uint32_t, uint32_t*, hipStream_t);
 template hipError_t pointwise_cls<ArF64S>(const ntt_plan_s*, int, void*, const void*, const void*,
                                          uint32_t, hipStream_t);
 template hipError_t polymul_cls<ArF64S>(const ntt_plan_s*, int, void*, const void*, const void*,

@@ -109,6 +109,19 @@ inline int polymul_rb_for(const ntt_plan_s* p, uint32_t split, uint32_t batch) {
   return (int)tuned_row_rb(4u, p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L, 3u);
 }
 
+// Single-launch two-pass form (both passes in one persistent launch): for
+// splits with 2^12-word rows and 2..16 columns per transform; forced by
+// NTT_FLAG_FUSED, else off.
+inline bool fused_shape_ok(const ntt_plan_s* p, uint32_t split) {
+  return split >= 1 && split <= 4 && p->log_n == split + 12;
+}
+inline bool fused_for(const ntt_plan_s* p, bool inv, uint32_t split, uint32_t batch) {
+  (void)inv;
+  (void)batch;
+  if (!fused_shape_ok(p, split)) return false;
+  return (p->flags & NTT_FLAG_FUSED) != 0;
+}
+
 // Split used by one call over `batch` polynomials.
 inline uint32_t call_split(const ntt_plan_s* p, uint32_t batch) {
   if (p->forced_split >= 0) return (uint32_t)p->forced_split;

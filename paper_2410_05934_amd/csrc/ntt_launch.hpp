@@ -5,6 +5,7 @@
 
 #include <algorithm>
 
+#include "fused.hpp"
 #include "ntt_internal.hpp"
 #include "ntt_kernels.hpp"
 
@@ -139,12 +140,83 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   return a;
 }
 
+// Single-launch two-pass transform (row length 2^12): persistent grid of the
+// workgroups resident at once, list lag from the grid.
+template <class A, int LOGN1, bool INV, int RB>
+hipError_t launch_fused_n(FusedArgs a, int device, hipStream_t s) {
+  using S = RowShape<12, RB>;
+  // resident workgroups per CU (one gfx950 build: the same on every device)
+  static const int per_cu = []() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<A, LOGN1, 12, INV, RB>,
+                                                     S::BLOCK, 0) != hipSuccess || nb < 1)
+      nb = 1;
+    return nb;
+  }();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  // forward: columns first (pieces of BLOCK columns), then rows; inverse: rows
+  // first, then columns
+  const uint32_t col_pieces = (1u << 12) / S::BLOCK, row_pieces = 1u << LOGN1;
+  a.p1 = INV ? row_pieces : col_pieces;
+  a.p2 = INV ? col_pieces : row_pieces;
+  a.total = a.n_tr * (a.p1 + a.p2);
+  const uint32_t grid = std::min<uint32_t>(a.total, (uint32_t)(cus * per_cu));
+  const uint32_t want = (3 * grid + 2 * (a.p1 + a.p2) - 1) / (2 * (a.p1 + a.p2));
+  a.lag = std::max<uint32_t>(1u, std::min<uint32_t>(a.n_tr, want));
+  LaunchTimer t(RB == 4 ? "fused" : "fused8", A::kName, LOGN1 + 12, INV, true,
+                (uint64_t)a.n_tr << (LOGN1 + 12), s);
+  hipLaunchKernelGGL((fused_kernel<A, LOGN1, 12, INV, RB>), dim3(grid), dim3(S::BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class A, bool INV>
+hipError_t launch_fused(int n1, const FusedArgs& a, int device, hipStream_t s, int rb) {
+  if (rb == 3) {
+    switch (n1) {
+      case 1: return launch_fused_n<A, 1, INV, 3>(a, device, s);
+      case 2: return launch_fused_n<A, 2, INV, 3>(a, device, s);
+      case 3: return launch_fused_n<A, 3, INV, 3>(a, device, s);
+      case 4: return launch_fused_n<A, 4, INV, 3>(a, device, s);
+      default: break;
+    }
+  } else {
+    switch (n1) {
+      case 1: return launch_fused_n<A, 1, INV, 4>(a, device, s);
+      case 2: return launch_fused_n<A, 2, INV, 4>(a, device, s);
+      case 3: return launch_fused_n<A, 3, INV, 4>(a, device, s);
+      case 4: return launch_fused_n<A, 4, INV, 4>(a, device, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// `work` (nullptr: two launches) holds the counters of the single-launch form
+// for every class of the plan: class c uses 1 + batch * cls_cnt[c] words at
+// offset batch * cls_off[c] + c.
 template <class A>
 hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
-                         uint32_t split, hipStream_t s) {
+                         uint32_t split, uint32_t* work, hipStream_t s) {
   const int n = p->log_n, n1 = (int)split, n2 = n - n1;
   const int rb = row_rb_for(p, inv, split, batch);
   hipError_t e = hipSuccess;
+  if (work && fused_shape_ok(p, split)) {
+    FusedArgs fa;
+    fa.data = data;
+    fa.limbs = p->d_limbs;
+    fa.cls_limbs = p->d_cls_limbs + p->cls_off[c];
+    fa.L = p->L;
+    fa.batch = batch;
+    fa.log_n = p->log_n;
+    fa.n_tr = batch * p->cls_cnt[c];
+    fa.spin_limit = 1u << 20;
+    fa.work = work + (size_t)batch * p->cls_off[c] + c;
+    return inv ? launch_fused<A, true>(n1, fa, p->device, s, rb)
+               : launch_fused<A, false>(n1, fa, p->device, s, rb);
+  }
   if (n1 == 0) {
     RowArgs a = row_args(p, c, data, data, nullptr, batch, n1);
     e = inv ? launch_row<A, true, false>(n2, a, s, rb) : launch_row<A, false, false>(n2, a, s, rb);

@@ -157,7 +157,7 @@ static void free_plan(ntt_plan_s* p) {
 namespace nttk {
 template <class A>
 hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
-                         uint32_t split, hipStream_t s);
+                         uint32_t split, uint32_t* work, hipStream_t s);
 template <class A>
 hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
                          uint32_t batch, hipStream_t s);
@@ -169,7 +169,7 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
                    uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
 #define NTT_EXTERN_CLASS(A)                                                                   \
   extern template hipError_t transform_cls<A>(const ntt_plan_s*, int, void*, uint32_t, bool,  \
-                                              uint32_t, hipStream_t);                         \
+                                              uint32_t, uint32_t*, hipStream_t);              \
   extern template hipError_t pointwise_cls<A>(const ntt_plan_s*, int, void*, const void*,     \
                                               const void*, uint32_t, hipStream_t);            \
   extern template hipError_t polymul_cls<A>(const ntt_plan_s*, int, void*, const void*,       \
@@ -194,6 +194,37 @@ NTT_EXTERN_CLASS(ArI64)
       if (e_ != hipSuccess) return hip_fail(e_, "kernel launch");                \
     }                                                                            \
   } while (0)
+
+static __global__ void fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Forward or inverse over every class of the plan.  The single-launch form
+// needs 1 + batch * cls_cnt[c] zeroed counters per class (one stream-ordered
+// allocation, cleared by a fill kernel so that the call can be captured).
+static ntt_status transform_entry(ntt_plan_t plan, void* data, uint32_t batch, bool inv,
+                                  hipStream_t s) {
+  const uint32_t split = call_split(plan, batch);
+  uint32_t* work = nullptr;
+  if (fused_for(plan, inv, split, batch)) {
+    const uint32_t n = batch * plan->L + 3;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&work), (size_t)n * 4, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(single-launch counters)");
+    hipLaunchKernelGGL(fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, work, n, 0u);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+      (void)hipFreeAsync(work, s);
+      return hip_fail(e, "counter fill");
+    }
+  }
+  const ntt_status rc = [&]() -> ntt_status {
+    NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, inv, split, work, s)));
+    return NTT_OK;
+  }();
+  if (work) (void)hipFreeAsync(work, s);
+  return rc;
+}
 
 static ntt_status check_plan_batch(ntt_plan_t p, uint32_t batch) {
   if (!p) return fail(NTT_EINVAL, "null plan");
@@ -314,10 +345,7 @@ ntt_status ntt_forward(ntt_plan_t plan, void* data, uint32_t batch, void* stream
   ntt_status st = check_plan_batch(plan, batch);
   if (st != NTT_OK) return st;
   if (!data) return fail(NTT_EINVAL, "null data");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint32_t split = call_split(plan, batch);
-  NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, false, split, s)));
-  return NTT_OK;
+  return transform_entry(plan, data, batch, false, static_cast<hipStream_t>(stream));
 }
 
 ntt_status ntt_inverse(ntt_plan_t plan, void* data, uint32_t batch, void* stream) {
@@ -325,10 +353,7 @@ ntt_status ntt_inverse(ntt_plan_t plan, void* data, uint32_t batch, void* stream
   ntt_status st = check_plan_batch(plan, batch);
   if (st != NTT_OK) return st;
   if (!data) return fail(NTT_EINVAL, "null data");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint32_t split = call_split(plan, batch);
-  NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, true, split, s)));
-  return NTT_OK;
+  return transform_entry(plan, data, batch, true, static_cast<hipStream_t>(stream));
 }
 
 ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const void* b,

@@ -284,3 +284,44 @@ def test_tuning_table_radix16_rows_are_bit_identical(cls, logn, tmp_path):
         assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
     finally:
         ntt.tune_clear()
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64", "mixed64"])
+@pytest.mark.parametrize("logn", [13, 14, 15, 16])
+@pytest.mark.parametrize("batch", [1, 3])
+def test_single_launch_two_pass_is_bit_identical(cls, logn, batch):
+    """Both passes in one persistent launch (per-transform counters) give the
+    oracle's words, forward and inverse, radix-16 and radix-8 rows."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    a = _data(300 + logn + batch, moduli, batch, N, word_bits)
+    want_f = oracle.forward(a, moduli)
+    want_i = oracle.inverse(a, moduli)
+    for extra in (0, ntt.FLAG_ROW_RADIX8):
+        plan = ntt.Plan(N, moduli, word_bits, flags=ntt.FLAG_FUSED | extra)
+        assert np.array_equal(_run_fwd(plan, a, word_bits), want_f), extra
+        assert np.array_equal(_run_inv(plan, a, word_bits), want_i), extra
+
+
+def test_single_launch_full_c2_shape_matches_two_launches():
+    """4 x 36 x 2^16 (the CKKS-shaped workload): the single-launch form gives the
+    same words as the two-launch form for forward and inverse, and the oracle's
+    words on sampled limb-rows."""
+    mods = synth.c2_primes(36)
+    N = 1 << 16
+    a = synth.uniform_poly(5, mods, 4, N)
+    two = ntt.Plan(N, mods, 64)
+    one = ntt.Plan(N, mods, 64, flags=ntt.FLAG_FUSED)
+    d1, d2 = to_device(a, 64), to_device(a, 64)
+    two.forward(d1)
+    one.forward(d2)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2)
+    f = to_host(d2, 64)
+    for (b, l) in [(0, 0), (1, 17), (3, 35), (2, 8)]:
+        assert np.array_equal(f[b:b + 1, l:l + 1], oracle.forward(a[b:b + 1, l:l + 1], [mods[l]]))
+    two.inverse(d1)
+    one.inverse(d2)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2)
+    assert np.array_equal(to_host(d2, 64), a)
