@@ -125,7 +125,8 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const vo
  *   key   [rows][cols][L][N]
  *   out   [groups][cols][L][N], groups = ceil(num_operands / rows)
  *   out[g][c] = sum over the rows r present in group g of a[g*rows + r] (.) key[r][c]
- * The last group may be partial.  out must not alias a or key. */
+ * The last group may be partial.  out must not alias a or key; out and key
+ * must each hold fewer than 2^32 words (else NTT_EINVAL). */
 ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, uint32_t rows,
                    uint32_t cols, uint32_t num_operands, void* stream);
 

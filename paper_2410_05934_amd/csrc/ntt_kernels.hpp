@@ -88,7 +88,7 @@ struct MacArgs {
   uint32_t L;
   uint32_t log_n;
   uint32_t rows, cols, num_operands, groups;
-  uint64_t total;            // groups * n_cls * N
+  uint64_t total;            // groups * cols * n_cls * N
 };
 
 // Padded LDS index: one spare slot after every 16 (spreads strided accesses
@@ -607,70 +607,132 @@ col_kernel(ColArgs args) {
 }
 
 // ---------------------------------------------------------------------------
-// Elementwise product c = a (.) b on [batch][L][N] (NTT domain).
+// VEC consecutive words at p: one 16-byte access when VEC words make 16 bytes
+// (the caller guarantees 16-byte alignment then), else VEC word accesses.
+template <class W, int VEC>
+__device__ __forceinline__ void load_words(W (&x)[VEC], const W* p_in) {
+  if constexpr (VEC * sizeof(W) == 16) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = *(const NTT_GLOBAL u32x4*)p_in;
+    const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      if constexpr (sizeof(W) == 8) x[k] = (W)d[2 * k] | ((W)d[2 * k + 1] << 32);
+      else x[k] = (W)d[k];
+    }
+  } else {
+    const NTT_GLOBAL W* p = (const NTT_GLOBAL W*)p_in;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) x[k] = p[k];
+  }
+}
+
+template <class W, int VEC>
+__device__ __forceinline__ void store_words(W* p_out, const W (&x)[VEC]) {
+  if constexpr (VEC * sizeof(W) == 16) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    uint32_t d[4];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      if constexpr (sizeof(W) == 8) {
+        d[2 * k] = (uint32_t)x[k];
+        d[2 * k + 1] = (uint32_t)(x[k] >> 32);
+      } else {
+        d[k] = (uint32_t)x[k];
+      }
+    }
+    u32x4 v;
+    v.x = d[0];
+    v.y = d[1];
+    v.z = d[2];
+    v.w = d[3];
+    *(NTT_GLOBAL u32x4*)p_out = v;
+  } else {
+    NTT_GLOBAL W* p = (NTT_GLOBAL W*)p_out;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) p[k] = x[k];
+  }
+}
+
+// Elementwise product c = a (.) b on [batch][L][N] (NTT domain).  Each thread
+// takes VEC consecutive words of one limb-row: VEC = 16 / sizeof(word) gives one
+// 16-byte load per operand and one 16-byte store (the host picks VEC = 1 when N
+// is shorter or a pointer is not 16-byte aligned).
 constexpr int kEltBlock = 256;
 
-template <class A>
+template <class A, int VEC>
 __global__ void __launch_bounds__(kEltBlock)
 pointwise_kernel(EltArgs args) {
   using W = typename A::W;
-  const uint64_t n = 1ull << args.log_n;
-  for (uint64_t i = blockIdx.x * (uint64_t)kEltBlock + threadIdx.x; i < args.total;
-       i += (uint64_t)gridDim.x * kEltBlock) {
-    const uint64_t j = i & (n - 1);
-    const uint64_t rest = i >> args.log_n;
-    const uint32_t li = (uint32_t)(rest % args.n_cls);
-    const uint64_t poly = rest / args.n_cls;
-    const uint32_t limb = args.cls_limbs[li];
-    const LimbDev& ld = args.limbs[limb];
-    const A ar(ld);
-    const uint64_t off = ((poly * args.L + limb) << args.log_n) + j;
-    const W x = reinterpret_cast<const W*>(args.a)[off];
-    const W y = reinterpret_cast<const W*>(args.b)[off];
-    reinterpret_cast<W*>(args.dst)[off] = ar.to_word(ar.mul(ar.from_word(x), ar.from_word(y)));
-  }
+  const uint32_t e = (blockIdx.x * kEltBlock + threadIdx.x) * VEC;
+  if (e >= args.total) return;
+  const uint32_t row = e >> args.log_n;
+  const uint32_t li = row % args.n_cls;
+  const uint32_t poly = row / args.n_cls;
+  const uint32_t limb = args.cls_limbs[li];
+  const A ar(args.limbs[limb]);
+  const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) +
+                       (e & ((1u << args.log_n) - 1u));
+  W x[VEC], y[VEC], z[VEC];
+  load_words<W, VEC>(x, reinterpret_cast<const W*>(args.a) + off);
+  load_words<W, VEC>(y, reinterpret_cast<const W*>(args.b) + off);
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) z[k] = ar.to_word(ar.mul(ar.from_word(x[k]), ar.from_word(y[k])));
+  store_words<W, VEC>(reinterpret_cast<W*>(args.dst) + off, z);
 }
 
 // Grouped multiply-accumulate (external-product MAC in the NTT domain):
 // out[g][c] = sum over rows r present in group g of a[g*rows + r] (.) key[r][c].
-template <class A>
+// One thread per VEC consecutive words of one (group, column, limb) row.  Rows
+// are taken kMacRows at a time with every load issued before the products (the
+// rows beyond the group's end are computed and dropped by a select, so no
+// branch holds a load back).
+constexpr int kMacRows = 8;
+
+template <class A, int VEC>
 __global__ void __launch_bounds__(kEltBlock)
 mac_kernel(MacArgs args) {
   using W = typename A::W;
   using V = typename A::V;
-  const uint64_t n = 1ull << args.log_n;
-  for (uint64_t i = blockIdx.x * (uint64_t)kEltBlock + threadIdx.x; i < args.total;
-       i += (uint64_t)gridDim.x * kEltBlock) {
-    const uint64_t j = i & (n - 1);
-    const uint64_t rest = i >> args.log_n;
-    const uint32_t li = (uint32_t)(rest % args.n_cls);
-    const uint32_t grp = (uint32_t)(rest / args.n_cls);
-    const uint32_t limb = args.cls_limbs[li];
-    const LimbDev& ld = args.limbs[limb];
-    const A ar(ld);
-    const W* a = reinterpret_cast<const W*>(args.a);
-    const W* key = reinterpret_cast<const W*>(args.key);
-    W* out = reinterpret_cast<W*>(args.dst);
-    const uint64_t limb_off = ((uint64_t)limb << args.log_n) + j;
-    for (uint32_t c = 0; c < args.cols; ++c) {
-      V acc{};
-      bool first = true;
-      for (uint32_t r = 0; r < args.rows; ++r) {
-        const uint32_t p = grp * args.rows + r;
-        if (p >= args.num_operands) break;
-        const V x = ar.from_word(a[(uint64_t)p * args.L * n + limb_off]);
-        const V k = ar.from_word(key[((uint64_t)r * args.cols + c) * args.L * n + limb_off]);
-        const V prod = ar.mul(x, k);
-        if (first) {
-          acc = prod;
-          first = false;
-        } else {
-          acc = ar.add(acc, prod);
-        }
+  const uint32_t e = (blockIdx.x * kEltBlock + threadIdx.x) * VEC;
+  if (e >= args.total) return;
+  const uint32_t row = e >> args.log_n;  // (group * cols + c) * n_cls + li
+  const uint32_t li = row % args.n_cls;
+  const uint32_t gc = row / args.n_cls;
+  const uint32_t c = gc % args.cols;
+  const uint32_t grp = gc / args.cols;
+  const uint32_t limb = args.cls_limbs[li];
+  const A ar(args.limbs[limb]);
+  const uint64_t poly_words = (uint64_t)args.L << args.log_n;
+  const uint64_t limb_off = ((uint64_t)limb << args.log_n) + (e & ((1u << args.log_n) - 1u));
+  const uint32_t first = grp * args.rows;
+  const uint32_t nr = min(args.rows, args.num_operands - first);
+  const W* a = reinterpret_cast<const W*>(args.a);
+  const W* key = reinterpret_cast<const W*>(args.key);
+  V acc[VEC];
+  for (uint32_t r0 = 0; r0 < nr; r0 += kMacRows) {
+    W x[kMacRows][VEC], k[kMacRows][VEC];
+#pragma unroll
+    for (int i = 0; i < kMacRows; ++i) {
+      const uint32_t r = r0 + i < nr ? r0 + i : r0;  // in range; dropped below
+      load_words<W, VEC>(x[i], a + (uint64_t)(first + r) * poly_words + limb_off);
+      load_words<W, VEC>(k[i], key + ((uint64_t)r * args.cols + c) * poly_words + limb_off);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load above the products
+#pragma unroll
+    for (int i = 0; i < kMacRows; ++i) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const V prod = ar.mul(ar.from_word(x[i][v]), ar.from_word(k[i][v]));
+        const V sum = (r0 + i == 0) ? prod : ar.add(acc[v], prod);
+        acc[v] = (r0 + i < nr) ? sum : acc[v];
       }
-      out[((uint64_t)grp * args.cols + c) * args.L * n + limb_off] = ar.to_word(acc);
     }
   }
+  W z[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) z[v] = ar.to_word(acc[v]);
+  store_words<W, VEC>(reinterpret_cast<W*>(args.dst) + (uint64_t)gc * poly_words + limb_off, z);
 }
 
 }  // namespace nttk

@@ -253,11 +253,15 @@ hipError_t pointwise_cls(const ntt_plan_s* p, int c, void* out, const void* a,
   ea.n_cls = p->cls_cnt[c];
   ea.L = p->L;
   ea.log_n = p->log_n;
-  ea.total = ((uint64_t)batch * p->cls_cnt[c]) << p->log_n;
-  const uint64_t want = (ea.total + kEltBlock - 1) / kEltBlock;
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256ull * 64);
+  ea.total = ((uint64_t)batch * p->cls_cnt[c]) << p->log_n;  // < 2^32 (checked by the caller)
+  constexpr int kVec = 16 / (int)sizeof(typename A::W);
+  auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+  const bool vec = (1u << p->log_n) >= (uint32_t)kVec && aligned(out) && aligned(a) && aligned(b);
+  const int per = vec ? kVec : 1;
+  const uint32_t blocks = (uint32_t)((ea.total / per + kEltBlock - 1) / kEltBlock);
   LaunchTimer t("pointwise", A::kName, p->log_n, false, false, ea.total, s);
-  hipLaunchKernelGGL((pointwise_kernel<A>), dim3(blocks), dim3(kEltBlock), 0, s, ea);
+  if (vec) hipLaunchKernelGGL((pointwise_kernel<A, kVec>), dim3(blocks), dim3(kEltBlock), 0, s, ea);
+  else hipLaunchKernelGGL((pointwise_kernel<A, 1>), dim3(blocks), dim3(kEltBlock), 0, s, ea);
   return hipGetLastError();
 }
 
@@ -307,11 +311,15 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
   m.cols = cols;
   m.num_operands = num_operands;
   m.groups = (num_operands + rows - 1) / rows;
-  m.total = ((uint64_t)m.groups * p->cls_cnt[c]) << p->log_n;
-  const uint64_t want = (m.total + kEltBlock - 1) / kEltBlock;
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(want, 256ull * 64);
+  m.total = ((uint64_t)m.groups * cols * p->cls_cnt[c]) << p->log_n;  // < 2^32 (checked)
+  constexpr int kVec = 16 / (int)sizeof(typename A::W);
+  auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+  const bool vec = (1u << p->log_n) >= (uint32_t)kVec && aligned(out) && aligned(a) && aligned(key);
+  const int per = vec ? kVec : 1;
+  const uint32_t blocks = (uint32_t)((m.total / per + kEltBlock - 1) / kEltBlock);
   LaunchTimer t("mac", A::kName, p->log_n, false, false, m.total, s);
-  hipLaunchKernelGGL((mac_kernel<A>), dim3(blocks), dim3(kEltBlock), 0, s, m);
+  if (vec) hipLaunchKernelGGL((mac_kernel<A, kVec>), dim3(blocks), dim3(kEltBlock), 0, s, m);
+  else hipLaunchKernelGGL((mac_kernel<A, 1>), dim3(blocks), dim3(kEltBlock), 0, s, m);
   return hipGetLastError();
 }
 

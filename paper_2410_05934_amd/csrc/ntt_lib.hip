@@ -374,6 +374,12 @@ ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, u
   if (st != NTT_OK) return st;
   if (!out || !a || !key) return fail(NTT_EINVAL, "null data");
   if (rows == 0 || cols == 0) return fail(NTT_EINVAL, "rows and cols must be >= 1");
+  {
+    const uint64_t groups = ((uint64_t)num_operands + rows - 1) / rows;
+    const uint64_t poly = (uint64_t)plan->L << plan->log_n;
+    if (groups * cols * poly >= (1ull << 32) || (uint64_t)rows * cols * poly >= (1ull << 32))
+      return fail(NTT_EINVAL, "out and key must each hold < 2^32 words");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   NTT_FOR_CLASSES(plan, (mac_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s)));
   return NTT_OK;

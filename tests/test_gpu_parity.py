@@ -325,3 +325,44 @@ def test_single_launch_full_c2_shape_matches_two_launches():
     torch.cuda.synchronize()
     assert torch.equal(d1, d2)
     assert np.array_equal(to_host(d2, 64), a)
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+def test_pointwise_with_operands_not_16_byte_aligned(cls):
+    """Operands one word past a 16-byte boundary take the one-word-per-thread path
+    and give the same words."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << 10
+    a = _data(41, moduli, 2, N, word_bits)
+    b = _data(42, moduli, 2, N, word_bits)
+    n = a.size
+    fa = torch.zeros(n + 1, dtype=torch.int64 if word_bits == 64 else torch.int32, device="cuda")
+    fb, fo = torch.zeros_like(fa), torch.zeros_like(fa)
+    da, db, do = fa[1:].view(a.shape), fb[1:].view(a.shape), fo[1:].view(a.shape)
+    da.copy_(to_device(a, word_bits))
+    db.copy_(to_device(b, word_bits))
+    plan = ntt.Plan(N, moduli, word_bits)
+    plan.pointwise_mul(do, da, db)
+    torch.cuda.synchronize()
+    assert do.data_ptr() % 16 != 0
+    assert np.array_equal(to_host(do, word_bits).astype(np.uint64), oracle.pointwise_mul(a, b, moduli))
+    assert int(fo[0].item()) == 0
+
+
+@pytest.mark.parametrize("cls", list(CLASSES))
+@pytest.mark.parametrize("logn,P,rows,cols", [(1, 5, 2, 3), (3, 7, 3, 2), (10, 13, 6, 2), (12, 4, 4, 1)])
+def test_mac_matches_oracle(cls, logn, P, rows, cols):
+    """Grouped MAC for every class, with a partial last group where P % rows != 0."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    a = _data(51 + logn, moduli, P, N, word_bits)
+    key = _data(52 + logn, moduli, rows * cols, N, word_bits).reshape(rows, cols, len(moduli), N)
+    G = (P + rows - 1) // rows
+    plan = ntt.Plan(N, moduli, word_bits)
+    da = to_device(a, word_bits)
+    dk = to_device(key.reshape(rows * cols, len(moduli), N), word_bits)
+    out = empty_device((G * cols, len(moduli), N), word_bits)
+    plan.mac(out, da, dk, rows, cols)
+    torch.cuda.synchronize()
+    want = oracle.mac(a, key, moduli, rows, cols).reshape(G * cols, len(moduli), N)
+    assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want)
