@@ -130,6 +130,22 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const vo
 ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, uint32_t rows,
                    uint32_t cols, uint32_t num_operands, void* stream);
 
+/* External product of the TFHE CMux (Sec. II-B, Sec. IV-A: decomposed operands
+ * are transformed, multiplied-and-accumulated against a key in the transform
+ * domain, and the accumulators are inverse-transformed):
+ *   out[g][c] = INTT( sum over the rows r present in group g of
+ *                     NTT(a[g*rows + r]) (.) key[r][c] )
+ * with the grouping of ntt_mac.  a [num_operands][L][N] in natural order (not
+ * modified), key [rows][cols][L][N] in the transform domain (the order
+ * ntt_forward produces), out [groups][cols][L][N] in natural order; out must
+ * not alias a or key.  The same words as ntt_forward on a copy of a, ntt_mac
+ * and ntt_inverse on out.  For N <= 2^12 with cols <= rows (and a workgroup of
+ * rows * N/16 <= 1024 threads) one launch does everything per group and limb;
+ * other shapes take the three steps through a stream-ordered workspace. */
+ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const void* key,
+                                uint32_t rows, uint32_t cols, uint32_t num_operands,
+                                void* stream);
+
 /* Negacyclic product c = a * b mod (x^N + 1) per limb, through Eq. (1):
  * out, a, b are [batch][L][N] in natural order; a and b are not modified;
  * out must not alias a or b. */

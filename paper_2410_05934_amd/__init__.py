@@ -64,6 +64,7 @@ _SIGS = {
     "ntt_inverse": [_vp, _vp, _u32, _vp],
     "ntt_pointwise_mul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_mac": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
@@ -432,6 +433,19 @@ class Plan:
             raise ValueError("out must hold ceil(P/rows)*cols polynomials")
         _check(lib().ntt_mac(self._h, out.data_ptr(), a.data_ptr(), key.data_ptr(), rows, cols, P,
                              _stream_handle(stream)), "ntt_mac")
+        return out
+
+    def external_product(self, out, a, key, rows: int, cols: int, stream=None):
+        """out[g][c] = INTT(sum_r NTT(a[g*rows + r]) (.) key[r][c]); a is not modified."""
+        P = self._batch_of(a, "a")
+        groups = (P + rows - 1) // rows
+        if self._batch_of(key, "key") != rows * cols:
+            raise ValueError("key must hold rows*cols polynomials")
+        if self._batch_of(out, "out") != groups * cols:
+            raise ValueError("out must hold ceil(P/rows)*cols polynomials")
+        _check(lib().ntt_external_product(self._h, out.data_ptr(), a.data_ptr(), key.data_ptr(),
+                                          rows, cols, P, _stream_handle(stream)),
+               "ntt_external_product")
         return out
 
     def polymul(self, out, a, b, stream=None):

@@ -122,6 +122,17 @@ inline bool fused_for(const ntt_plan_s* p, bool inv, uint32_t split, uint32_t ba
   return (p->flags & NTT_FLAG_FUSED) != 0;
 }
 
+// Fused external product (one launch per class): N = 2^4 .. 2^12, cols <= rows,
+// at most 1024 threads (rows * N/16) and 64 KiB of LDS (rows * (N + N/16)
+// values) per workgroup, key 16-byte aligned.
+inline bool xprod_fits(const ntt_plan_s* p, uint32_t rows, uint32_t cols, const void* key) {
+  if (p->log_n < 4 || p->log_n > 12 || cols > rows) return false;
+  const uint64_t n = 1ull << p->log_n;
+  if ((uint64_t)rows * (n / 16) > 1024) return false;
+  if ((uint64_t)rows * (n + n / 16) * 8 > 65536) return false;
+  return (reinterpret_cast<uintptr_t>(key) & 15u) == 0;
+}
+
 // Split used by one call over `batch` polynomials.
 inline uint32_t call_split(const ntt_plan_s* p, uint32_t batch) {
   if (p->forced_split >= 0) return (uint32_t)p->forced_split;

@@ -8,6 +8,7 @@
 #include "fused.hpp"
 #include "ntt_internal.hpp"
 #include "ntt_kernels.hpp"
+#include "xprod.hpp"
 
 namespace nttk {
 
@@ -321,6 +322,46 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
   if (vec) hipLaunchKernelGGL((mac_kernel<A, kVec>), dim3(blocks), dim3(kEltBlock), 0, s, m);
   else hipLaunchKernelGGL((mac_kernel<A, 1>), dim3(blocks), dim3(kEltBlock), 0, s, m);
   return hipGetLastError();
+}
+
+template <class A, int LOGN2>
+hipError_t launch_xprod_n(const XpArgs& x, uint32_t groups, hipStream_t s) {
+  using S = RowShape<LOGN2, 4>;
+  const uint32_t threads = x.rows * S::TPC;
+  const size_t lds = (size_t)x.rows * ((1u << LOGN2) + (1u << LOGN2) / 16) * sizeof(typename A::V);
+  LaunchTimer t("xprod", A::kName, LOGN2, false, false,
+                ((uint64_t)groups * x.cols * x.n_cls) << LOGN2, s);
+  hipLaunchKernelGGL((xprod_kernel<A, LOGN2>), dim3(groups * x.n_cls), dim3(threads), lds, s, x);
+  return hipGetLastError();
+}
+
+template <class A>
+hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
+                     uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s) {
+  XpArgs x;
+  x.dst = out;
+  x.a = a;
+  x.key = key;
+  x.limbs = p->d_limbs;
+  x.cls_limbs = p->d_cls_limbs + p->cls_off[c];
+  x.n_cls = p->cls_cnt[c];
+  x.L = p->L;
+  x.rows = rows;
+  x.cols = cols;
+  x.num_operands = num_operands;
+  const uint32_t groups = (num_operands + rows - 1) / rows;
+  switch (p->log_n) {
+    case 4: return launch_xprod_n<A, 4>(x, groups, s);
+    case 5: return launch_xprod_n<A, 5>(x, groups, s);
+    case 6: return launch_xprod_n<A, 6>(x, groups, s);
+    case 7: return launch_xprod_n<A, 7>(x, groups, s);
+    case 8: return launch_xprod_n<A, 8>(x, groups, s);
+    case 9: return launch_xprod_n<A, 9>(x, groups, s);
+    case 10: return launch_xprod_n<A, 10>(x, groups, s);
+    case 11: return launch_xprod_n<A, 11>(x, groups, s);
+    case 12: return launch_xprod_n<A, 12>(x, groups, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace nttk

@@ -167,6 +167,9 @@ hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, con
 template <class A>
 hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                    uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
+template <class A>
+hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
+                     uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
 #define NTT_EXTERN_CLASS(A)                                                                   \
   extern template hipError_t transform_cls<A>(const ntt_plan_s*, int, void*, uint32_t, bool,  \
                                               uint32_t, uint32_t*, hipStream_t);              \
@@ -176,7 +179,9 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
                                             const void*, void*, uint32_t, uint32_t,           \
                                             hipStream_t);                                     \
   extern template hipError_t mac_cls<A>(const ntt_plan_s*, int, void*, const void*,           \
-                                        const void*, uint32_t, uint32_t, uint32_t, hipStream_t);
+                                        const void*, uint32_t, uint32_t, uint32_t, hipStream_t); \
+  extern template hipError_t xprod_cls<A>(const ntt_plan_s*, int, void*, const void*,         \
+                                          const void*, uint32_t, uint32_t, uint32_t, hipStream_t);
 NTT_EXTERN_CLASS(ArF64S)
 NTT_EXTERN_CLASS(ArF64L)
 NTT_EXTERN_CLASS(ArI64)
@@ -383,6 +388,37 @@ ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, u
   hipStream_t s = static_cast<hipStream_t>(stream);
   NTT_FOR_CLASSES(plan, (mac_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s)));
   return NTT_OK;
+}
+
+ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const void* key,
+                                uint32_t rows, uint32_t cols, uint32_t num_operands, void* stream) {
+  clear_error();
+  ntt_status st = check_plan_batch(plan, num_operands);
+  if (st != NTT_OK) return st;
+  if (!out || !a || !key) return fail(NTT_EINVAL, "null data");
+  if (rows == 0 || cols == 0) return fail(NTT_EINVAL, "rows and cols must be >= 1");
+  if (out == a || out == key) return fail(NTT_EINVAL, "out must not alias a or key");
+  const uint64_t groups = ((uint64_t)num_operands + rows - 1) / rows;
+  const uint64_t poly = (uint64_t)plan->L << plan->log_n;
+  if (groups * cols * poly >= (1ull << 32) || (uint64_t)rows * cols * poly >= (1ull << 32))
+    return fail(NTT_EINVAL, "out and key must each hold < 2^32 words");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (xprod_fits(plan, rows, cols, key)) {
+    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s)));
+    return NTT_OK;
+  }
+  // Other shapes: forward a copy of the operands, MAC, inverse.
+  const size_t bytes = (size_t)num_operands * poly * (plan->word_bits / 8);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, bytes, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(external-product workspace)");
+  e = hipMemcpyAsync(ws, a, bytes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) st = hip_fail(e, "hipMemcpyAsync");
+  if (st == NTT_OK) st = ntt_forward(plan, ws, num_operands, stream);
+  if (st == NTT_OK) st = ntt_mac(plan, out, ws, key, rows, cols, num_operands, stream);
+  if (st == NTT_OK) st = ntt_inverse(plan, out, (uint32_t)(groups * cols), stream);
+  (void)hipFreeAsync(ws, s);
+  return st;
 }
 
 ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,

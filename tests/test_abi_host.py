@@ -34,6 +34,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_library_has_no_unresolved_internal_symbols():
+    """Every internal (nttk) symbol the library uses is defined in it: a function
+    declared in one translation unit and defined inline in another would only
+    fail when first called."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--undefined-only", ntt.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    assert "nttk" not in out, out
+
+
 def test_version_and_empty_error():
     lib = ntt.lib()
     assert b"gfx950" in lib.ntt_version()

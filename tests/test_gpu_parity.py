@@ -366,3 +366,33 @@ def test_mac_matches_oracle(cls, logn, P, rows, cols):
     torch.cuda.synchronize()
     want = oracle.mac(a, key, moduli, rows, cols).reshape(G * cols, len(moduli), N)
     assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("cls", list(CLASSES))
+@pytest.mark.parametrize("logn,P,rows,cols", [
+    (10, 2048, 6, 2),   # the TFHE-shaped batch: 342 groups, the last one partial
+    (4, 7, 3, 2), (6, 5, 5, 5), (8, 9, 4, 1), (12, 5, 4, 3),   # one launch
+    (12, 3, 8, 2),      # 8 slots of 2^12: more than 1024 threads -> three steps
+    (10, 4, 2, 3),      # cols > rows -> three steps
+    (13, 3, 2, 2), (2, 5, 2, 2)])  # N outside 2^4..2^12 -> three steps
+def test_external_product_matches_forward_mac_inverse(cls, logn, P, rows, cols):
+    """INTT(sum_r NTT(a_r) (.) key[r][c]) against the oracle's forward, MAC and
+    inverse; the operands are left unchanged."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    if cls == "u32" and logn == 10 and P == 2048:
+        moduli = moduli[:1]
+    a = _data(61 + logn + P, moduli, P, N, word_bits)
+    key = _data(62 + logn, moduli, rows * cols, N, word_bits).reshape(rows, cols, len(moduli), N)
+    G = (P + rows - 1) // rows
+    plan = ntt.Plan(N, moduli, word_bits)
+    da = to_device(a, word_bits)
+    dk = to_device(key.reshape(rows * cols, len(moduli), N), word_bits)
+    out = empty_device((G * cols, len(moduli), N), word_bits)
+    plan.external_product(out, da, dk, rows, cols)
+    torch.cuda.synchronize()
+    fa = oracle.forward(a, moduli)
+    acc = oracle.mac(fa, key, moduli, rows, cols).reshape(G * cols, len(moduli), N)
+    want = oracle.inverse(acc, moduli)
+    assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want)
+    assert np.array_equal(to_host(da, word_bits).astype(np.uint64), a)
