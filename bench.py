@@ -183,6 +183,22 @@ def run_gpu(args):
     extra = {"breakdown": breakdown, "ms_per_step_with_launch_events": round(ms_events, 4),
              "rotating_sets": args.sets, "split_used": plan.split_for(P), "tuned": tuned}
     if not args.no_aux:
+        # Whole transforms (forward alone, inverse alone) over the rotating sets:
+        # algorithmic bytes per C2 forward = every coefficient read and written
+        # once (144 x 1 MiB) plus one fp64 table of N entries per modulus (36 x 0.5 MiB).
+        import itertools
+        ctr = itertools.count()
+        t_fwd = _time(torch, lambda: plan.forward(X[next(ctr) % args.sets], stream), 4 * args.sets, stream)
+        t_inv = _time(torch, lambda: plan.inverse(X[next(ctr) % args.sets], stream), 4 * args.sets, stream)
+        coeff_bytes = 144 * 2 * N * 8
+        table_bytes = L * N * 8
+        whole = {}
+        for name, t in (("forward", t_fwd), ("inverse", t_inv)):
+            whole[name] = {"us": round(t * 1e3, 2), "limb_ntt_per_s": 144 / (t * 1e-3),
+                           "hbm_frac_coefficients": round(coeff_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "hbm_frac_with_tables": round((coeff_bytes + table_bytes) / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        _log(f"[bench] whole transforms: {whole}")
+        extra["c2_whole_transform"] = whole
         extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
     return value, ms_per_step, roofline, extra
 
@@ -231,14 +247,24 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
         for i in range(G * cols):
             p3.inverse(acc[i:i + 1], stream)
 
+    acc2 = empty_device((G * cols, 1, N), 32)
+
+    def c3_fused():
+        p3.external_product(acc2, a, key, rows, cols, stream)
+
     tb = _time(torch, c3_batched, 20, stream)
     tp = _time(torch, c3_plain, 3, stream)
+    tf = _time(torch, c3_fused, 20, stream)
     copy_ms = _time(torch, lambda: work.copy_(a), 20, stream)
+    torch.cuda.synchronize()
     n3 = Pn + G * cols
     out["c3_tfhe"] = {"batched_us": round(tb * 1e3, 2), "plain_us": round(tp * 1e3, 2),
                       "input_copy_us": round(copy_ms * 1e3, 2),
                       "batched_ntt_per_s": n3 / ((tb - copy_ms) * 1e-3),
-                      "batched_over_plain": round(tp / tb, 2)}
+                      "batched_over_plain": round(tp / tb, 2),
+                      "external_product_us": round(tf * 1e3, 2),
+                      "external_product_ntt_per_s": n3 / (tf * 1e-3),
+                      "external_product_same_words": bool(torch.equal(acc, acc2))}
     # C1 latency: one 2^10 forward + inverse, u32.
     q1 = synth.c1_prime(0)
     p1 = ntt.Plan(N, [q1], 32)
