@@ -275,7 +275,7 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
         out["c4_ragged"] = run_ragged(args, torch, ntt, synth, to_device, stream)
     if not args.no_serving:
         from paper_2410_05934_amd import serving
-        res = serving.sweep(args.serving_requests, [0.5, 0.9], 64 << 30, 4, args.seed, True)
+        res = serving.sweep(args.serving_requests, [0.1, 0.3, 0.5, 0.9], 64 << 30, 4, args.seed, True)
         keep = ("offered_rate", "achieved_req_per_s", "p50_ms", "p99_ms", "p99_ms_small",
                 "p99_ms_large", "mean_batch")
         out["c5_serving"] = {

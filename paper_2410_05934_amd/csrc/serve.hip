@@ -16,6 +16,7 @@
 // (Sec. IV-A, Tab. lut-opt) to raise utilisation and cut launches; this server
 // does the same for independent requests arriving over time.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -38,6 +39,7 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+constexpr int kPollUs = 4;       // completion polling interval of the server thread
 constexpr int kMaxCopies = 96;  // descriptors per gather/scatter launch (kernel-argument payload)
 
 struct CopyDesc {
@@ -372,8 +374,8 @@ struct ntt_server_s {
       }
       if (done.empty() && launched.empty()) {
         std::unique_lock<std::mutex> lk(mu);
-        // Poll in-flight work; wake early for new arrivals.
-        cv_work.wait_for(lk, std::chrono::microseconds(20));
+        // Poll in-flight work every few microseconds; wake early for new arrivals.
+        cv_work.wait_for(lk, std::chrono::microseconds(kPollUs));
       }
     }
   }
@@ -418,6 +420,9 @@ ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t 
     }
   }
   s->th = std::thread([s] {
+    // The loop polls in-flight launches with short timed waits; the default
+    // 50 us timer slack of a Linux thread would stretch every one of them.
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     if (!s->dry()) (void)hipSetDevice(s->device);
     s->loop();
   });
