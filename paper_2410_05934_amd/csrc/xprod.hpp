@@ -91,9 +91,16 @@ xprod_kernel(XpArgs args) {
   for (int u = 0; u < R; ++u) lds[MB::slot(tt, bb, u)] = v[u];
   __syncthreads();
 
-  // acc = sum over the group's rows of F_r (.) key[r][c].
+  // acc = sum over the group's rows of F_r (.) key[r][c].  When a slot spans
+  // whole waves (N >= 2^10), `busy` is wave-uniform and the slots without a
+  // column skip the products and the inverse arithmetic; they still take part
+  // in every barrier of the inverse's LDS exchanges.
+  constexpr bool kWaveSlots = S::TPC % 64 == 0;
+  const bool busy = !kWaveSlots || __builtin_amdgcn_readfirstlane(slot) < args.cols;
   V acc[R];
-  for (uint32_t r = 0; r < nr; ++r) {
+#pragma unroll
+  for (int u = 0; u < R; ++u) acc[u] = V{};
+  for (uint32_t r = 0; busy && r < nr; ++r) {
     W knext[R];
     if (r + 1 < nr) load_key(knext, r + 1);
     const V* fr = lds_all + r * kRegion;
@@ -110,8 +117,14 @@ xprod_kernel(XpArgs args) {
   __syncthreads();  // every slot has read the F regions before they are reused
 
   // Inverse transform of the accumulator; only the first `cols` slots store.
-  row_inverse_from<A, LOGN2, RB, S::K - 1, true>(
-      ar, acc, reinterpret_cast<const typename A::TW*>(ld.twi), 1u, tt, lds, ld);
+  if (busy) {
+    row_inverse_from<A, LOGN2, RB, S::K - 1, true>(
+        ar, acc, reinterpret_cast<const typename A::TW*>(ld.twi), 1u, tt, lds, ld);
+  } else {
+    // the barriers of the K - 1 exchanges (two each) in row_inverse_from
+#pragma unroll
+    for (int i = 0; i < 2 * (S::K - 1); ++i) __syncthreads();
+  }
   if (slot < args.cols) {
     W* dst = reinterpret_cast<W*>(args.dst) + ((uint64_t)grp * args.cols + slot) * poly_words +
              limb_off;
