@@ -396,3 +396,36 @@ def test_external_product_matches_forward_mac_inverse(cls, logn, P, rows, cols):
     want = oracle.inverse(acc, moduli)
     assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want)
     assert np.array_equal(to_host(da, word_bits).astype(np.uint64), a)
+
+
+def test_bad_sizes_and_arguments_are_rejected_before_any_launch():
+    """batch 0, batch * L * N >= 2^32 words, null data, aliasing and empty MAC
+    shapes return NTT_EINVAL (1) from the C ABI; nothing is launched."""
+    N = 1 << 16
+    plan = ntt.Plan(N, Q50[:1], 64)
+    a = empty_device((1, 1, N), 64)
+    b = empty_device((1, 1, N), 64)
+    lib = ntt.lib()
+    h = plan._h
+    EINVAL = 1
+    assert lib.ntt_forward(h, a.data_ptr(), 0, None) == EINVAL
+    assert lib.ntt_forward(h, a.data_ptr(), 1 << 16, None) == EINVAL     # exactly 2^32 words
+    assert lib.ntt_inverse(h, None, 1, None) == EINVAL
+    assert lib.ntt_pointwise_mul(h, a.data_ptr(), a.data_ptr(), None, 1, None) == EINVAL
+    assert lib.ntt_polymul(h, a.data_ptr(), a.data_ptr(), b.data_ptr(), 1, None) == EINVAL
+    assert lib.ntt_mac(h, a.data_ptr(), b.data_ptr(), b.data_ptr(), 0, 1, 1, None) == EINVAL
+    assert lib.ntt_external_product(h, a.data_ptr(), a.data_ptr(), b.data_ptr(), 1, 1, 1, None) == EINVAL
+    assert lib.ntt_external_product(h, a.data_ptr(), b.data_ptr(), b.data_ptr(), 1, 0, 1, None) == EINVAL
+    torch.cuda.synchronize()
+
+
+def test_a_thousand_limbs():
+    """A plan over 1000 distinct primes (N = 16, 40-bit primes, 64-bit words):
+    per-limb tables and class lists far beyond the configurations' 36 limbs."""
+    N = 16
+    mods = synth.primes_below(1 << 40, 2 * N, 1000)
+    a = _data(71, mods, 2, N, 64)
+    plan = ntt.Plan(N, mods, 64)
+    f = _run_fwd(plan, a, 64)
+    assert np.array_equal(f, oracle.forward(a, mods))
+    assert np.array_equal(_run_inv(plan, f, 64), a)
