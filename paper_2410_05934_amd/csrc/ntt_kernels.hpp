@@ -64,6 +64,8 @@ struct ColArgs {
   uint32_t log_n;
   uint32_t log_n2;           // row stages after this pass (0: whole transform)
   uint32_t total_cols;       // batch * n_cls * N2
+  void* dst2;                // optional second operand of the same shape (polymul's b):
+  const void* src2;          //   threads total_cols .. 2*total_cols-1 take it
 };
 
 struct EltArgs {
@@ -591,7 +593,14 @@ template <class A, int LOGN1, bool INV, bool TWO_PASS>
 __global__ void __launch_bounds__(kColBlock)
 col_kernel(ColArgs args) {
   using W = typename A::W;
-  const uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
+  uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
+  void* dst_base = args.dst;
+  const void* src_base = args.src;
+  if (args.src2 && gid >= args.total_cols) {
+    gid -= args.total_cols;
+    dst_base = args.dst2;
+    src_base = args.src2;
+  }
   const bool valid = gid < args.total_cols;
   const uint32_t g = valid ? gid : 0;
   const uint32_t n2 = 1u << args.log_n2;
@@ -601,8 +610,8 @@ col_kernel(ColArgs args) {
   const uint32_t poly = rest / args.n_cls;
   const uint32_t limb = args.cls_limbs[li];
   const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
-  col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(args.dst) + off,
-                                   reinterpret_cast<const W*>(args.src) + off, args.limbs[limb],
+  col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(dst_base) + off,
+                                   reinterpret_cast<const W*>(src_base) + off, args.limbs[limb],
                                    args.log_n2, valid);
 }
 

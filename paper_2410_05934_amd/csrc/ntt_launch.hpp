@@ -36,8 +36,9 @@ hipError_t launch_pm_n(const RowArgs& a, hipStream_t s) {
 
 template <class A, int LOGN1, bool INV, bool TWO>
 hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
-  const uint32_t blocks = (a.total_cols + kColBlock - 1) / kColBlock;
-  LaunchTimer t("col", A::kName, LOGN1, INV, TWO, (uint64_t)a.total_cols << LOGN1, s);
+  const uint64_t threads = (uint64_t)a.total_cols * (a.src2 ? 2 : 1);
+  const uint32_t blocks = (uint32_t)((threads + kColBlock - 1) / kColBlock);
+  LaunchTimer t("col", A::kName, LOGN1, INV, TWO, threads << LOGN1, s);
   hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(kColBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -138,6 +139,8 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.log_n = p->log_n;
   a.log_n2 = p->log_n - (uint32_t)n1;
   a.total_cols = (batch * p->cls_cnt[c]) << a.log_n2;
+  a.dst2 = nullptr;
+  a.src2 = nullptr;
   return a;
 }
 
@@ -286,9 +289,10 @@ hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, con
     ca = col_args(p, c, out, out, batch, n1);
     return launch_col<A, true, false>(n1, ca, s);
   }
+  // Column passes of a (into out) and b (into ws) in one launch.
   ColArgs ca = col_args(p, c, out, a, batch, n1);
-  if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
-  ca = col_args(p, c, ws, b, batch, n1);
+  ca.dst2 = ws;
+  ca.src2 = b;
   if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
   RowArgs ra = row_args(p, c, out, out, ws, batch, n1);
   if ((e = launch_pm<A, true>(n2, ra, s, rb)) != hipSuccess) return e;
