@@ -129,6 +129,16 @@ __device__ __forceinline__ const NTT_GLOBAL T* gptr(const T* p) {
   return (const NTT_GLOBAL T*)p;
 }
 
+// A pointer every lane of the wave holds, moved to scalar registers (so that
+// loads through it at uniform offsets can be scalar loads).
+template <class T>
+__device__ __forceinline__ const T* uniform_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
 // Local index of value u of thread tt when the thread holds the RB bits at hb.
 template <int RB = 4>
 __device__ __forceinline__ uint32_t ins_bits(uint32_t tt, uint32_t u, int hb) {
@@ -188,13 +198,16 @@ __device__ __forceinline__ void load_tw(TW (&w)[G], const TW* __restrict__ tab_i
 }
 
 // One forward (CT) stage on the R registers: local stage SP acts on u-bit B.
-template <class A, int RB, int B, int SP, int HB>
+// ZT: every thread of the chunk has tt >> HB == 0 (the chunk's first round),
+// so the twiddle index depends on the chunk alone -- a scalar load when the
+// caller made `base` and the table pointer wave-uniform.
+template <class A, int RB, int B, int SP, int HB, bool ZT = false>
 __device__ __forceinline__ void fwd_stage(const A& ar, typename A::V (&v)[1 << RB],
                                           const typename A::TW* __restrict__ tw, uint32_t base,
                                           uint32_t tt) {
   constexpr int G = 1 << (RB - 1 - B);
   typename A::TW w[G];
-  const uint32_t tg = (base << SP) + ((tt >> HB) << (RB - 1 - B));
+  const uint32_t tg = (base << SP) + (ZT ? 0u : ((tt >> HB) << (RB - 1 - B)));
   load_tw<typename A::TW, G>(w, tw, tg);
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -206,8 +219,9 @@ __device__ __forceinline__ void fwd_stage(const A& ar, typename A::V (&v)[1 << R
   }
 }
 
-// One inverse (GS) stage; FOLD applies N^-1 (only for global stage 0).
-template <class A, int RB, int B, int SP, int HB, bool FOLD>
+// One inverse (GS) stage; FOLD applies N^-1 (only for global stage 0); ZT as
+// for fwd_stage.
+template <class A, int RB, int B, int SP, int HB, bool FOLD, bool ZT = false>
 __device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[1 << RB],
                                           const typename A::TW* __restrict__ tw, uint32_t base,
                                           uint32_t tt, const LimbDev& ld) {
@@ -221,7 +235,7 @@ __device__ __forceinline__ void inv_stage(const A& ar, typename A::V (&v)[1 << R
     }
   } else {
     typename A::TW w[G];
-    const uint32_t tg = (base << SP) + ((tt >> HB) << (RB - 1 - B));
+    const uint32_t tg = (base << SP) + (ZT ? 0u : ((tt >> HB) << (RB - 1 - B)));
     load_tw<typename A::TW, G>(w, tw, tg);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -243,7 +257,7 @@ __device__ __forceinline__ void fwd_round_stages(const A& ar, typename A::V (&v)
     constexpr int HB = S::hb(J);
     constexpr int SP = RB * J + ST;
     constexpr int B = (LOGN2 - 1 - SP) - HB;
-    fwd_stage<A, RB, B, SP, HB>(ar, v, tw, base, tt);
+    fwd_stage<A, RB, B, SP, HB, (HB >= LOGN2 - RB)>(ar, v, tw, base, tt);
     fwd_round_stages<A, LOGN2, RB, J, ST + 1>(ar, v, tw, base, tt);
   }
 }
@@ -261,7 +275,7 @@ __device__ __forceinline__ void inv_round_stages(const A& ar, typename A::V (&v)
     if constexpr (FOLD && SP == 0) {
       inv_stage<A, RB, B, SP, HB, true>(ar, v, tw, base, tt, ld);
     } else {
-      inv_stage<A, RB, B, SP, HB, false>(ar, v, tw, base, tt, ld);
+      inv_stage<A, RB, B, SP, HB, false, (HB >= LOGN2 - RB)>(ar, v, tw, base, tt, ld);
     }
     inv_round_stages<A, LOGN2, RB, J, ST + 1, FOLD>(ar, v, tw, base, tt, ld);
   }
@@ -378,6 +392,15 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
   using V = typename A::V;
   using W = typename A::W;
   const A ar(ld);
+  // One chunk per workgroup: the chunk's twiddle base and tables are the same
+  // for every thread; say so, so the first round's twiddles are scalar loads.
+  const typename A::TW* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
+  const typename A::TW* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
+  if constexpr (S::CPW == 1) {
+    base = __builtin_amdgcn_readfirstlane(base);
+    twf = uniform_ptr(twf);
+    twi = uniform_ptr(twi);
+  }
   V v[R];
   if constexpr (!INV) {
     constexpr int H0 = S::hb(0);
@@ -386,7 +409,7 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
       const W x = src[ins_bits<RB>(tt, u, H0)];
       v[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
     }
-    const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twf);
+    const auto* tw = twf;
     row_forward_from<A, LOGN2, RB, 0>(ar, v, tw, base, tt, lds);
     if constexpr (S::K > 1) {
       // The last round holds R consecutive words per thread; re-deal them
@@ -429,7 +452,7 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
         ar.center(v[u]);
       }
     }
-    const auto* tw = reinterpret_cast<const typename A::TW*>(ld.twi);
+    const auto* tw = twi;
     row_inverse_from<A, LOGN2, RB, S::K - 1, !TWO_PASS>(ar, v, tw, base, tt, lds, ld);
     constexpr int H0 = S::hb(0);
     if (valid) {
@@ -449,7 +472,7 @@ row_kernel(RowArgs args) {
   using V = typename A::V;
   using W = typename A::W;
   __shared__ V lds_all[S::LDS_ELEMS];
-  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t ci = S::CPW == 1 ? 0u : threadIdx.x / S::TPC;
   const uint32_t tt = threadIdx.x & (S::TPC - 1);
   const ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
   row_chunk<A, LOGN2, INV, TWO_PASS, RB>(reinterpret_cast<W*>(args.dst) + cp.off,
@@ -470,9 +493,9 @@ polymul_row_kernel(RowArgs args) {
   using V = typename A::V;
   using W = typename A::W;
   __shared__ V lds_all[S::LDS_ELEMS];
-  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t ci = S::CPW == 1 ? 0u : threadIdx.x / S::TPC;
   const uint32_t tt = threadIdx.x & (S::TPC - 1);
-  const ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
+  ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
   const LimbDev& ld = args.limbs[cp.limb];
   const A ar(ld);
   V* lds = lds_all + ci * S::CHUNK_LDS;
@@ -481,6 +504,11 @@ polymul_row_kernel(RowArgs args) {
   W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + cp.off;
   const auto* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
   const auto* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
+  if constexpr (S::CPW == 1) {  // one chunk per workgroup: uniform base and tables
+    cp.base = __builtin_amdgcn_readfirstlane(cp.base);
+    twf = uniform_ptr(twf);
+    twi = uniform_ptr(twi);
+  }
   constexpr int H0 = S::hb(0);
   V va[R], vb[R];
 #pragma unroll
