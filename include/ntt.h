@@ -69,8 +69,8 @@ typedef enum {
 #define NTT_FLAG_FORCE_INT64 (1u << 16)
 /* Row passes of 2^10 .. 2^13 words with 8 values per thread (radix-8 rounds,
  * twice the threads of radix-16 rounds, one more LDS exchange).  Without it the
- * tuning table chooses per direction and shape, else radix-8 for inverse and
- * polymul rows and radix-16 for forward rows. */
+ * tuning table chooses per direction and shape, else radix-8 for inverse rows
+ * and single-pass polymul rows, radix-16 for forward and two-pass polymul rows. */
 #define NTT_FLAG_ROW_RADIX8 (1u << 17)
 /* Two-pass transforms with 2^12-word rows (N = 2^13 .. 2^16) run both passes in
  * one persistent launch: the one global synchronisation per transform of the

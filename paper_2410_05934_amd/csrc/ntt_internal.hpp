@@ -84,8 +84,8 @@ uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback);
 bool split_valid(int log_n, int n1);
 
 // Values per thread (log2) of row passes: forced by NTT_FLAG_ROW_RADIX8, else the
-// tuning table, else radix-8 for inverse and polymul rows of 2^10..2^13 words (more
-// waves to hide their early loads) and radix-16 for forward rows.
+// tuning table, else radix-8 for inverse rows and single-pass polymul rows of
+// 2^10..2^13 words and radix-16 for forward rows and two-pass polymul rows.
 uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback);
 inline int dominant_class(const ntt_plan_s* p) {
   uint32_t best = 0, cnt = 0;
@@ -106,7 +106,10 @@ inline int polymul_rb_for(const ntt_plan_s* p, uint32_t split, uint32_t batch) {
   const int n2 = (int)p->log_n - (int)split;
   if (n2 < 10 || n2 > 13) return 4;
   if (p->row_rb) return p->row_rb;
-  return (int)tuned_row_rb(4u, p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L, 3u);
+  // measured on 2 x 36 x 2^16: radix-16 rows 46 us, radix-8 52 us (two-pass)
+  const uint32_t fallback = split ? 4u : 3u;
+  return (int)tuned_row_rb(4u, p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L,
+                           fallback);
 }
 
 // Single-launch two-pass form (both passes in one persistent launch): for

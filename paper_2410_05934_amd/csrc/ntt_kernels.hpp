@@ -334,6 +334,68 @@ __device__ __forceinline__ void row_inverse_from(const A& ar, typename A::V (&v)
   }
 }
 
+// Forward stages of two operands of the same chunk (polymul's a and b): each
+// stage's twiddles are loaded once and applied to both, and the two butterfly
+// streams interleave.
+template <class A, int RB, int B, int SP, int HB, bool ZT>
+__device__ __forceinline__ void fwd_stage2(const A& ar, typename A::V (&va)[1 << RB],
+                                           typename A::V (&vb)[1 << RB],
+                                           const typename A::TW* __restrict__ tw, uint32_t base,
+                                           uint32_t tt) {
+  constexpr int G = 1 << (RB - 1 - B);
+  typename A::TW w[G];
+  const uint32_t tg = (base << SP) + (ZT ? 0u : ((tt >> HB) << (RB - 1 - B)));
+  load_tw<typename A::TW, G>(w, tw, tg);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int i = 0; i < (1 << B); ++i) {
+      const int lo = (g << (B + 1)) | i;
+      ar.ct(va[lo], va[lo | (1 << B)], w[g]);
+      ar.ct(vb[lo], vb[lo | (1 << B)], w[g]);
+    }
+  }
+}
+
+template <class A, int LOGN2, int RB, int J, int ST>
+__device__ __forceinline__ void fwd_round_stages2(const A& ar, typename A::V (&va)[1 << RB],
+                                                  typename A::V (&vb)[1 << RB],
+                                                  const typename A::TW* __restrict__ tw,
+                                                  uint32_t base, uint32_t tt) {
+  using S = RowShape<LOGN2, RB>;
+  if constexpr (ST < S::nst(J)) {
+    constexpr int HB = S::hb(J);
+    constexpr int SP = RB * J + ST;
+    constexpr int B = (LOGN2 - 1 - SP) - HB;
+    fwd_stage2<A, RB, B, SP, HB, (HB >= LOGN2 - RB)>(ar, va, vb, tw, base, tt);
+    fwd_round_stages2<A, LOGN2, RB, J, ST + 1>(ar, va, vb, tw, base, tt);
+  }
+}
+
+template <class A, int LOGN2, int RB, int J>
+__device__ __forceinline__ void row_forward2_from(const A& ar, typename A::V (&va)[1 << RB],
+                                                  typename A::V (&vb)[1 << RB],
+                                                  const typename A::TW* __restrict__ tw,
+                                                  uint32_t base, uint32_t tt, typename A::V* lds) {
+  using S = RowShape<LOGN2, RB>;
+  if constexpr (J < S::K) {
+    fwd_round_stages2<A, LOGN2, RB, J, 0>(ar, va, vb, tw, base, tt);
+    if constexpr (J + 1 < S::K) {
+      if constexpr (A::kCenterRounds) {
+#pragma unroll
+        for (int u = 0; u < S::R; ++u) {
+          ar.center(va[u]);
+          ar.center(vb[u]);
+        }
+      }
+      // one LDS region: the two re-deals take turns
+      lds_exchange<A, LOGN2, RB, J, J + 1>(va, lds, tt);
+      lds_exchange<A, LOGN2, RB, J, J + 1>(vb, lds, tt);
+      row_forward2_from<A, LOGN2, RB, J + 1>(ar, va, vb, tw, base, tt, lds);
+    }
+  }
+}
+
 // Chunk bookkeeping shared by the row kernels.
 struct ChunkPos {
   uint64_t off;     // word offset of the chunk
@@ -514,15 +576,11 @@ polymul_row_kernel(RowArgs args) {
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const W x = sa[ins_bits<RB>(tt, u, H0)];
+    const W y = sb[ins_bits<RB>(tt, u, H0)];
     va[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
+    vb[u] = TWO_PASS ? ar.from_raw(y) : ar.from_word(y);
   }
-  row_forward_from<A, LOGN2, RB, 0>(ar, va, twf, cp.base, tt, lds);
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const W x = sb[ins_bits<RB>(tt, u, H0)];
-    vb[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
-  }
-  row_forward_from<A, LOGN2, RB, 0>(ar, vb, twf, cp.base, tt, lds);
+  row_forward2_from<A, LOGN2, RB, 0>(ar, va, vb, twf, cp.base, tt, lds);
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     va[u] = ar.mul(va[u], vb[u]);
