@@ -280,7 +280,8 @@ ntt_status ntt_server_destroy(ntt_server_t s);
 
 /* Time every admissible pass split for (N, moduli, word_bits) on `batch`
  * polynomials of scratch data (forward + inverse, HIP events on an internal
- * stream), record the fastest in the library's tuning table and return it.
+ * stream, the fastest of three timed groups per configuration), record the
+ * fastest in the library's tuning table and return it.
  * Later calls with a similar number of limb-rows (same power-of-two bucket of
  * batch * L) and no forced split use it.  The paper's switch trigger (chunks
  * closest to the SM count, Sec. V-D) is for one polynomial; a batch changes the
