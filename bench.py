@@ -397,9 +397,9 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(every (poly, limb) transform is independent; see the sharding notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (every "
+              "(poly, limb) transform is independent, so limbs would be dealt to GPUs "
+              "round-robin with no exchange). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     value, ms_per_step, roofline, extra = run_gpu(args)
     cpu = None if args.no_cpu else run_cpu_baseline(args)
