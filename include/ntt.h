@@ -148,7 +148,11 @@ ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const
 
 /* Negacyclic product c = a * b mod (x^N + 1) per limb, through Eq. (1):
  * out, a, b are [batch][L][N] in natural order; a and b are not modified;
- * out must not alias a or b. */
+ * out must not alias a or b.  A two-pass product (N above the single-pass
+ * length) takes a workspace of batch * L * N words from the device's default
+ * memory pool, stream-ordered (hipMallocAsync / hipFreeAsync on `stream`);
+ * callers that issue many products on several streams at once may prefer to
+ * batch them per stream, as the request server does with its own arenas. */
 ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,
                        void* stream);
 

@@ -142,4 +142,11 @@ inline uint32_t call_split(const ntt_plan_s* p, uint32_t batch) {
   return tuned_split_for(p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L, p->log_n1);
 }
 
+// Polymul with a caller-provided workspace of polymul_ws_bytes(p, batch) bytes
+// (none needed when that is 0): the same launches as ntt_polymul without its
+// stream-ordered allocation.  No argument checks beyond the workspace.
+size_t polymul_ws_bytes(const ntt_plan_s* p, uint32_t batch);
+ntt_status polymul_into(const ntt_plan_s* p, void* out, const void* a, const void* b,
+                        uint32_t batch, void* ws, hipStream_t s);
+
 }  // namespace nttk

@@ -231,6 +231,21 @@ static ntt_status transform_entry(ntt_plan_t plan, void* data, uint32_t batch, b
   return rc;
 }
 
+namespace nttk {
+size_t polymul_ws_bytes(const ntt_plan_s* p, uint32_t batch) {
+  const uint32_t split = polymul_split(p, call_split(p, batch));
+  return split ? ((size_t)batch * p->L << p->log_n) * (p->word_bits / 8) : 0;
+}
+
+ntt_status polymul_into(const ntt_plan_s* plan, void* out, const void* a, const void* b,
+                        uint32_t batch, void* ws, hipStream_t s) {
+  const uint32_t split = polymul_split(plan, call_split(plan, batch));
+  if (split && !ws) return fail(NTT_EINVAL, "polymul workspace missing");
+  NTT_FOR_CLASSES(plan, (polymul_cls<A>(plan, c, out, a, b, ws, batch, split, s)));
+  return NTT_OK;
+}
+}  // namespace nttk
+
 static ntt_status check_plan_batch(ntt_plan_t p, uint32_t batch) {
   if (!p) return fail(NTT_EINVAL, "null plan");
   if (batch == 0) return fail(NTT_EINVAL, "batch must be >= 1");
@@ -430,18 +445,13 @@ ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b,
   if (out == a || out == b) return fail(NTT_EINVAL, "out must not alias a or b");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = nullptr;
-  const uint32_t split = polymul_split(plan, call_split(plan, batch));
-  const bool need_ws = split != 0;
-  if (need_ws) {
-    const size_t bytes = ((size_t)batch * plan->L << plan->log_n) * (plan->word_bits / 8);
+  const size_t bytes = polymul_ws_bytes(plan, batch);
+  if (bytes) {
     hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(polymul workspace)");
   }
-  const ntt_status rc = [&]() -> ntt_status {
-    NTT_FOR_CLASSES(plan, (polymul_cls<A>(plan, c, out, a, b, ws, batch, split, s)));
-    return NTT_OK;
-  }();
-  if (need_ws) (void)hipFreeAsync(ws, s);
+  const ntt_status rc = polymul_into(plan, out, a, b, batch, ws, s);
+  if (ws) (void)hipFreeAsync(ws, s);
   return rc;
 }
 

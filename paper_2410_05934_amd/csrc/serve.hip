@@ -118,6 +118,7 @@ struct ntt_server_s {
   // later batch on the same stream runs after the earlier one's scatter).
   std::vector<void*> arena;
   std::vector<size_t> arena_bytes;
+  std::vector<hipEvent_t> free_events;  // completion events, reused (server thread only)
   uint32_t max_reqs = 64;  // requests per launch
   std::map<std::tuple<uint32_t, uint32_t, std::vector<uint64_t>>, ntt_plan_t> plans;
 
@@ -175,11 +176,27 @@ struct ntt_server_s {
     const bool host = q0->r.memory == NTT_REQ_HOST;
     const bool single = b->reqs.size() == 1 && !host;
     hipError_t e = hipSuccess;
+    // Grow this stream's arena to `need` bytes: wait for its earlier batches,
+    // then reallocate (rare: the arena keeps its largest size).
+    auto reserve = [&](size_t need) -> hipError_t {
+      if (arena_bytes[b->stream] >= need) return hipSuccess;
+      hipError_t r = hipStreamSynchronize(s);
+      if (r == hipSuccess && arena[b->stream]) r = hipFree(arena[b->stream]);
+      arena[b->stream] = nullptr;
+      arena_bytes[b->stream] = 0;
+      const size_t grow = std::max(need, (size_t)64 << 20);
+      if (r == hipSuccess) r = hipMalloc(&arena[b->stream], grow);
+      if (r == hipSuccess) arena_bytes[b->stream] = grow;
+      return r;
+    };
     if (single) {
-      // Operands are resident: run in place on the request's own buffers.
+      // Operands are resident: run in place on the request's own buffers; a
+      // two-pass polymul takes its workspace from the stream's arena.
       const Req* q = q0;
       if (pm) {
-        st = ntt_polymul(plan, q->r.out, q->r.a, q->r.b, q->r.batch, s);
+        const size_t ws = polymul_ws_bytes(plan, q->r.batch);
+        if (ws && (e = reserve(ws)) != hipSuccess) return hip_fail(e, "server staging allocation");
+        st = polymul_into(plan, q->r.out, q->r.a, q->r.b, q->r.batch, ws ? arena[b->stream] : nullptr, s);
       } else {
         if (q->r.out != q->r.a)
           e = hipMemcpyAsync(q->r.out, q->r.a, q->words * wb, hipMemcpyDeviceToDevice, s);
@@ -189,22 +206,15 @@ struct ntt_server_s {
       }
     } else {
       // Gather every operand into one contiguous batch, run one launch, scatter.
+      // Arena layout: A | B | O | polymul workspace (polymul), A (transforms).
       const uint64_t total = (uint64_t)polys * per * wb;
-      const size_t need = (size_t)total * (pm ? 3 : 1);
-      if (arena_bytes[b->stream] < need) {
-        // Grow: wait for this stream's earlier batches, then reallocate.
-        e = hipStreamSynchronize(s);
-        if (e == hipSuccess && arena[b->stream]) e = hipFree(arena[b->stream]);
-        arena[b->stream] = nullptr;
-        arena_bytes[b->stream] = 0;
-        const size_t grow = std::max(need, (size_t)64 << 20);
-        if (e == hipSuccess) e = hipMalloc(&arena[b->stream], grow);
-        if (e != hipSuccess) return hip_fail(e, "server staging allocation");
-        arena_bytes[b->stream] = grow;
-      }
+      const size_t ws = pm ? polymul_ws_bytes(plan, polys) : 0;
+      const size_t need = (size_t)total * (pm ? 3 : 1) + ws;
+      if ((e = reserve(need)) != hipSuccess) return hip_fail(e, "server staging allocation");
       void* A = arena[b->stream];
       void* B = pm ? static_cast<unsigned char*>(A) + total : nullptr;
       void* O = pm ? static_cast<unsigned char*>(A) + 2 * total : nullptr;
+      void* WS = ws ? static_cast<unsigned char*>(A) + 3 * total : nullptr;
       std::vector<CopyDesc> in;
       uint64_t off = 0;
       for (Req* q : b->reqs) {
@@ -226,7 +236,7 @@ struct ntt_server_s {
       }
       if (!in.empty() && (e = copy_many(in, s)) != hipSuccess) return hip_fail(e, "server gather");
       void* res = pm ? O : A;
-      if (pm) st = ntt_polymul(plan, O, A, B, polys, s);
+      if (pm) st = polymul_into(plan, O, A, B, polys, WS, s);
       else st = q0->r.op == NTT_REQ_FORWARD ? ntt_forward(plan, A, polys, s) : ntt_inverse(plan, A, polys, s);
       if (st != NTT_OK) return st;
       std::vector<CopyDesc> outc;
@@ -246,7 +256,12 @@ struct ntt_server_s {
     }
     if (st != NTT_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "server launch");
-    e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (!free_events.empty()) {
+      b->ev = free_events.back();
+      free_events.pop_back();
+    } else {
+      e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipEventRecord(b->ev, s);
     return e == hipSuccess ? NTT_OK : hip_fail(e, "server event");
   }
@@ -266,7 +281,7 @@ struct ntt_server_s {
     }
     inflight_bytes -= b->bytes;
     stream_load[b->stream] -= 1;
-    if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->ev) free_events.push_back(b->ev);
     delete b;
   }
 
@@ -530,6 +545,7 @@ ntt_status ntt_server_destroy(ntt_server_t s) {
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (void* a : s->arena)
     if (a) (void)hipFree(a);
+  for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
   for (auto& kv : s->plans) ntt_plan_destroy(kv.second);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   delete s;
