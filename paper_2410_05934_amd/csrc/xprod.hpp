@@ -81,8 +81,10 @@ xprod_kernel(XpArgs args) {
   V v[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) v[u] = ar.from_word(src[ins_bits<RB>(tt, u, H0)]);
-  row_forward_from<A, LOGN2, RB, 0>(ar, v, reinterpret_cast<const typename A::TW*>(ld.twf), 1u,
-                                    tt, lds);
+  // One limb per workgroup: the tables are wave-uniform (scalar first-round twiddles).
+  const typename A::TW* twf = uniform_ptr(reinterpret_cast<const typename A::TW*>(ld.twf));
+  const typename A::TW* twi = uniform_ptr(reinterpret_cast<const typename A::TW*>(ld.twi));
+  row_forward_from<A, LOGN2, RB, 0>(ar, v, twf, 1u, tt, lds);
   // Publish F_slot: thread tt holds positions tt*R + u (the last round's layout).
   using MB = LdsMap<RB, 0>;
   const uint32_t bb = MB::base(tt);
@@ -118,8 +120,7 @@ xprod_kernel(XpArgs args) {
 
   // Inverse transform of the accumulator; only the first `cols` slots store.
   if (busy) {
-    row_inverse_from<A, LOGN2, RB, S::K - 1, true>(
-        ar, acc, reinterpret_cast<const typename A::TW*>(ld.twi), 1u, tt, lds, ld);
+    row_inverse_from<A, LOGN2, RB, S::K - 1, true>(ar, acc, twi, 1u, tt, lds, ld);
   } else {
     // the barriers of the K - 1 exchanges (two each) in row_inverse_from
 #pragma unroll
