@@ -454,11 +454,12 @@ __device__ __forceinline__ void row_chunk(typename A::W* __restrict__ dst,
   using V = typename A::V;
   using W = typename A::W;
   const A ar(ld);
-  // One chunk per workgroup: the chunk's twiddle base and tables are the same
-  // for every thread; say so, so the first round's twiddles are scalar loads.
+  // When a chunk spans whole waves (N2/R a multiple of 64), the chunk's twiddle
+  // base and tables are the same in every lane of a wave; say so, so the first
+  // round's twiddles are scalar loads.
   const typename A::TW* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
   const typename A::TW* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
-  if constexpr (S::CPW == 1) {
+  if constexpr (S::TPC % 64 == 0) {
     base = __builtin_amdgcn_readfirstlane(base);
     twf = uniform_ptr(twf);
     twi = uniform_ptr(twi);
@@ -566,7 +567,7 @@ polymul_row_kernel(RowArgs args) {
   W* __restrict__ dst = reinterpret_cast<W*>(args.dst) + cp.off;
   const auto* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
   const auto* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
-  if constexpr (S::CPW == 1) {  // one chunk per workgroup: uniform base and tables
+  if constexpr (S::TPC % 64 == 0) {  // a chunk spans whole waves: wave-uniform base and tables
     cp.base = __builtin_amdgcn_readfirstlane(cp.base);
     twf = uniform_ptr(twf);
     twi = uniform_ptr(twi);
