@@ -84,8 +84,9 @@ __device__ __noinline__ void ragged_two_pass(const RaggedJobDev* jp, const Ragge
       col_one<A, LOGN1, INV, true>(p + r, p + r, ld, LOGN2, true);
   };
   auto rows = [&]() {
+    // the workgroup's kRaggedBlock threads hold kRaggedBlock / TPC chunks at a time
 #pragma unroll 1
-    for (uint32_t c0 = 0; c0 < N1; c0 += S::CPW) {
+    for (uint32_t c0 = 0; c0 < N1; c0 += kRaggedBlock / S::TPC) {
       const uint32_t c = c0 + ci;
       const bool valid = c < N1;
       W* q = p + ((uint64_t)(valid ? c : 0) << LOGN2);
