@@ -76,7 +76,11 @@ typedef enum {
  * one persistent launch: the one global synchronisation per transform of the
  * paper's single-kernel hybrid NTT (Sec. V-D) becomes a per-transform counter
  * that row (forward) or column (inverse) pieces wait on.  Results are
- * bit-identical to the two-launch form. */
+ * bit-identical to the two-launch form.  The waits are bounded (about 2^20
+ * polls); the order of the work list guarantees that they end long before, and
+ * the output would be unspecified if one ever expired.  On MI355X this form is
+ * slower than the default two launches (cross-XCD release/acquire per piece);
+ * it is there for callers that need a single launch per call. */
 #define NTT_FLAG_FUSED (1u << 18)
 
 /* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
