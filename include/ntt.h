@@ -177,23 +177,30 @@ typedef struct ntt_ragged_s* ntt_ragged_t;
 
 /* ntt_ragged_create flags. */
 #define NTT_RAGGED_NO_GRAPH (1u << 0)           /* launch directly instead of replaying a hipGraph */
-#define NTT_RAGGED_ROW_LOG(n2) (((uint32_t)(n2) & 0xfu) << 8) /* force row length 2^n2 (11 or 12) for N >= 2^13 */
+#define NTT_RAGGED_IN_WORKGROUP (1u << 1)       /* N >= 2^13 too in the persistent kernel (below) */
+#define NTT_RAGGED_ROW_LOG(n2) (((uint32_t)(n2) & 0xfu) << 8) /* with NTT_RAGGED_IN_WORKGROUP: row length 2^n2 (11 or 12) */
 
 /* Build a reusable ragged batch over jobs[0 .. n-1] (the paper's single kernel
- * launch for the hybrid NTT, Sec. V-D, applied to a mixed batch).  The work list
- * -- one limb-row per item, or up to 16 rows of one small N -- is built on the
- * host, sorted largest first and uploaded once.  The plans and data buffers
- * named by the jobs must stay valid for the life of the handle.  Jobs of 32-bit
- * and 64-bit words run as one persistent launch per width. */
+ * launch for the hybrid NTT, Sec. V-D, applied to a mixed batch).  Transforms of
+ * N <= 2^12 form a work list -- up to 16 limb-rows of one small N per item --
+ * built on the host, sorted largest first, uploaded once and run by one
+ * persistent launch per word width.  Transforms of N >= 2^13 are grouped by
+ * (N, arithmetic class, direction): every limb-row of a group goes into one row
+ * table and one column launch plus one row launch cover the group, as the
+ * batched transform does for one plan.  With NTT_RAGGED_IN_WORKGROUP they go
+ * into the persistent kernel too instead (one workgroup per transform, the
+ * intermediate kept with its CU).  The plans and data buffers named by the jobs
+ * must stay valid for the life of the handle. */
 ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n, uint32_t flags);
 
 /* Run the batch on `stream`: reset the work counter and launch the persistent
- * kernel(s).  Unless NTT_RAGGED_NO_GRAPH was given, the first run captures these
- * launches into a hipGraph and every run replays it.  Runs of one handle must
- * not overlap in time (they share the work counter). */
+ * kernel(s) and the grouped launches.  Unless NTT_RAGGED_NO_GRAPH was given, the
+ * first run captures these launches into a hipGraph and every run replays it.
+ * Runs of one handle must not overlap in time (they share the work counter). */
 ntt_status ntt_ragged_run(ntt_ragged_t r, void* stream);
 
-/* Work items and persistent workgroups of a batch. */
+/* Work items of a batch (persistent-kernel items plus the limb-rows of the
+ * grouped launches) and persistent workgroups. */
 ntt_status ntt_ragged_info(ntt_ragged_t r, uint32_t* items, uint32_t* workgroups);
 
 ntt_status ntt_ragged_destroy(ntt_ragged_t r);
@@ -301,7 +308,8 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
                           uint32_t word_bits, uint32_t batch, uint32_t* best_n1, float* best_us);
 
 /* Time row lengths 2^11 and 2^12 for the in-workgroup split of ragged batches
- * with this N (>= 2^13) and record the faster; returns log2 of the row length. */
+ * (NTT_RAGGED_IN_WORKGROUP) with this N (>= 2^13) and record the faster;
+ * returns log2 of the row length. */
 ntt_status ntt_tune_ragged(uint32_t N, const uint64_t* moduli, uint32_t num_moduli,
                            uint32_t batch, uint32_t* best_row_log, float* best_us);
 

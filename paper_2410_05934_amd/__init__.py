@@ -17,7 +17,7 @@ import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
            "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_FUSED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
-           "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH",
+           "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
            "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
            "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
            "SERVER_SERIAL", "SERVER_DRY_RUN"]
@@ -96,6 +96,7 @@ _SIGS = {
 OP_FORWARD = 0
 OP_INVERSE = 1
 RAGGED_NO_GRAPH = 1
+RAGGED_IN_WORKGROUP = 1 << 1
 
 
 def ragged_row_log(n2: int) -> int:

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -182,6 +183,82 @@ __global__ void __launch_bounds__(kRaggedBlock, 4) ragged_kernel(RaggedArgs args
   }
 }
 
+// ---------------------------------------------------------------------------
+// Grouped two-pass launches for the large transforms of a batch (N >= 2^13):
+// every limb-row of one (N, class, direction) goes into one row table, and one
+// column launch plus one row launch (2^12-word rows) cover all of them, as the
+// batched transform does for one plan.  Table rows are sorted by prime, and
+// row chunks are ordered row-fastest, so neighbouring workgroups share twiddles.
+struct RowRef {
+  void* data;          // 2^log_n words of one limb-row
+  const LimbDev* ld;   // its modulus (device copy inside the owning plan)
+};
+
+struct GangArgs {
+  const RowRef* rows;
+  uint32_t n_rows;
+  uint32_t log_n1;     // column stages; rows are 2^12 words
+};
+
+constexpr int kGangLogN2 = 12;
+
+template <class A, int LOGN1, bool INV>
+__global__ void __launch_bounds__(kColBlock) gang_col_kernel(GangArgs g) {
+  using W = typename A::W;
+  const uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
+  const bool valid = gid < (g.n_rows << kGangLogN2);
+  const uint32_t x = valid ? gid : 0;
+  const RowRef rr = g.rows[x >> kGangLogN2];
+  W* p = reinterpret_cast<W*>(rr.data) + (x & ((1u << kGangLogN2) - 1u));
+  col_one<A, LOGN1, INV, true>(p, p, *rr.ld, kGangLogN2, valid);
+}
+
+template <class A, bool INV>
+__global__ void __launch_bounds__((RowShape<kGangLogN2, 4>::BLOCK), 4) gang_row_kernel(GangArgs g) {
+  using S = RowShape<kGangLogN2, 4>;
+  static_assert(S::CPW == 1, "one chunk per workgroup");
+  using V = typename A::V;
+  using W = typename A::W;
+  __shared__ V lds[S::LDS_ELEMS];
+  const uint32_t total = g.n_rows << g.log_n1;
+  const uint32_t k0 = xcd_block(blockIdx.x, gridDim.x);
+  const bool valid = k0 < total;
+  const uint32_t k = valid ? k0 : 0;
+  const uint32_t i = k % g.n_rows, c = k / g.n_rows;
+  const RowRef rr = g.rows[i];
+  W* p = reinterpret_cast<W*>(rr.data) + ((uint64_t)c << kGangLogN2);
+  row_chunk<A, kGangLogN2, INV, true, 4>(p, p, *rr.ld, (1u << g.log_n1) + c, threadIdx.x, lds,
+                                         valid);
+}
+
+template <class A, bool INV>
+hipError_t launch_gang(const GangArgs& g, hipStream_t s, bool timed) {
+  const uint32_t cols = g.n_rows << kGangLogN2;
+  const uint32_t chunks = g.n_rows << g.log_n1;
+  const uint64_t words = (uint64_t)g.n_rows << (g.log_n1 + kGangLogN2);
+  auto col = [&]() -> hipError_t {
+    LaunchTimer t(timed ? "gang_col" : nullptr, A::kName, (int)g.log_n1, INV, true, words, s);
+    const dim3 grid((cols + kColBlock - 1) / kColBlock);
+    switch (g.log_n1) {
+      case 1: hipLaunchKernelGGL((gang_col_kernel<A, 1, INV>), grid, dim3(kColBlock), 0, s, g); break;
+      case 2: hipLaunchKernelGGL((gang_col_kernel<A, 2, INV>), grid, dim3(kColBlock), 0, s, g); break;
+      case 3: hipLaunchKernelGGL((gang_col_kernel<A, 3, INV>), grid, dim3(kColBlock), 0, s, g); break;
+      case 4: hipLaunchKernelGGL((gang_col_kernel<A, 4, INV>), grid, dim3(kColBlock), 0, s, g); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  auto row = [&]() -> hipError_t {
+    LaunchTimer t(timed ? "gang_row" : nullptr, A::kName, kGangLogN2, INV, true, words, s);
+    hipLaunchKernelGGL((gang_row_kernel<A, INV>), dim3(chunks),
+                       dim3(RowShape<kGangLogN2, 4>::BLOCK), 0, s, g);
+    return hipGetLastError();
+  };
+  hipError_t e = INV ? row() : col();
+  if (e == hipSuccess) e = INV ? col() : row();
+  return e;
+}
+
 __global__ void zero_counters(uint32_t* c, uint32_t n) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) c[i] = 0;
@@ -200,6 +277,12 @@ struct ntt_ragged_s {
   RaggedItem* d_items = nullptr;
   uint32_t* d_counter = nullptr;  // [2]
   uint32_t grid[2] = {0, 0};
+  // grouped launches of the N >= 2^13 transforms
+  struct Gang {
+    uint32_t cls, log_n, inv, off, n;
+  };
+  std::vector<Gang> gangs;
+  RowRef* d_rows = nullptr;
   bool use_graph = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -215,10 +298,36 @@ uint32_t ragged_split_for(uint32_t log_n, uint32_t flags) {
   return tuned_ragged_row_log(log_n, 12);
 }
 
-hipError_t launch_all(ntt_ragged_s* r, hipStream_t s, bool timed) {
+// Launch everything on `s`; with `branches` (graph capture), each group of
+// large transforms runs on its own stream forked from and joined back to `s`,
+// so the captured graph has the groups and the persistent kernel as parallel
+// branches (they touch disjoint data).
+hipError_t launch_all(ntt_ragged_s* r, hipStream_t s, bool timed,
+                      const std::vector<hipStream_t>* branches = nullptr) {
+  hipError_t e = hipSuccess;
+  std::vector<hipEvent_t> events;  // fork, then one join per branch
+  auto cleanup = [&]() {
+    for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+  };
+  const bool fork = branches && !branches->empty() && !r->gangs.empty();
+  if (fork) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) events.push_back(ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, s);
+    for (size_t b = 0; e == hipSuccess && b < branches->size(); ++b)
+      e = hipStreamWaitEvent((*branches)[b], ev, 0);
+    if (e != hipSuccess) {
+      cleanup();
+      return e;
+    }
+  }
   hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, s, r->d_counter, 2u);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    cleanup();
+    return e;
+  }
   for (int w = 0; w < 2; ++w) {
     if (r->n_items[w] == 0) continue;
     RaggedArgs a;
@@ -230,9 +339,37 @@ hipError_t launch_all(ntt_ragged_s* r, hipStream_t s, bool timed) {
     if (w) hipLaunchKernelGGL(ragged_kernel<true>, dim3(r->grid[w]), dim3(kRaggedBlock), 0, s, a);
     else hipLaunchKernelGGL(ragged_kernel<false>, dim3(r->grid[w]), dim3(kRaggedBlock), 0, s, a);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      cleanup();
+      return e;
+    }
   }
-  return hipSuccess;
+  for (size_t i = 0; i < r->gangs.size(); ++i) {
+    const auto& gg = r->gangs[i];
+    hipStream_t gs = fork ? (*branches)[i % branches->size()] : s;
+    GangArgs g;
+    g.rows = r->d_rows + gg.off;
+    g.n_rows = gg.n;
+    g.log_n1 = gg.log_n - kGangLogN2;
+    if (gg.cls == 0) e = gg.inv ? launch_gang<ArF64S, true>(g, gs, timed) : launch_gang<ArF64S, false>(g, gs, timed);
+    else if (gg.cls == 1) e = gg.inv ? launch_gang<ArF64L, true>(g, gs, timed) : launch_gang<ArF64L, false>(g, gs, timed);
+    else e = gg.inv ? launch_gang<ArI64, true>(g, gs, timed) : launch_gang<ArI64, false>(g, gs, timed);
+    if (e != hipSuccess) {
+      cleanup();
+      return e;
+    }
+  }
+  if (fork) {
+    for (size_t b = 0; e == hipSuccess && b < branches->size(); ++b) {
+      hipEvent_t ev = nullptr;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) events.push_back(ev);
+      if (e == hipSuccess) e = hipEventRecord(ev, (*branches)[b]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    }
+  }
+  cleanup();
+  return e;
 }
 
 void free_ragged(ntt_ragged_s* r) {
@@ -242,6 +379,7 @@ void free_ragged(ntt_ragged_s* r) {
   if (r->d_jobs) (void)hipFree(r->d_jobs);
   if (r->d_items) (void)hipFree(r->d_items);
   if (r->d_counter) (void)hipFree(r->d_counter);
+  if (r->d_rows) (void)hipFree(r->d_rows);
   delete r;
 }
 
@@ -261,6 +399,9 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
     return hip_fail(e, "hipGetDevice");
   }
   std::vector<RaggedItem> wide, narrow;
+  const bool in_wg = (flags & NTT_RAGGED_IN_WORKGROUP) != 0;
+  // (class, log_n, inv) -> (twiddle table address, row) for the grouped launches
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<std::pair<uint64_t, RowRef>>> groups;
   for (uint32_t ji = 0; ji < n; ++ji) {
     const ntt_job& jb = jobs[ji];
     if (!jb.plan || !jb.data || jb.batch == 0 || jb.op > 1) {
@@ -284,6 +425,19 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
     jd.log_n2 = ragged_split_for(p->log_n, flags);
     jd.inv = jb.op;
     r->jobs.push_back(jd);
+    if (p->log_n > 12 && !in_wg) {
+      const size_t wbytes = p->word_bits / 8;
+      for (uint32_t b = 0; b < jb.batch; ++b)
+        for (uint32_t l = 0; l < p->L; ++l) {
+          RowRef rr;
+          rr.data = static_cast<unsigned char*>(jb.data) +
+                    (((uint64_t)b * p->L + l) << p->log_n) * wbytes;
+          rr.ld = p->d_limbs + l;
+          groups[std::make_tuple((uint32_t)p->cls[l], p->log_n, jb.op)].push_back(
+              {reinterpret_cast<uint64_t>(p->h_limbs[l].twf), rr});
+        }
+      continue;
+    }
     const uint32_t per = p->log_n <= 12 ? std::min<uint32_t>(kRaggedRows, std::max<uint32_t>(1u, kRaggedBlock / ((1u << p->log_n) / 16)))
                                         : 1u;
     // Group rows of the same limb class; rows run b-major then l.
@@ -312,6 +466,27 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
   auto by_cost = [&](const RaggedItem& a, const RaggedItem& b) { return cost(a) > cost(b); };
   std::stable_sort(narrow.begin(), narrow.end(), by_cost);
   std::stable_sort(wide.begin(), wide.end(), by_cost);
+  std::vector<RowRef> table;
+  for (auto& kv : groups) {
+    auto& v = kv.second;
+    if (((uint64_t)v.size() << std::get<1>(kv.first)) >= (1ull << 32)) {
+      free_ragged(r);
+      return fail(NTT_EINVAL, "a group of 2^%u-word rows holds 2^32 words or more",
+                  std::get<1>(kv.first));
+    }
+    std::stable_sort(v.begin(), v.end(), [](const std::pair<uint64_t, RowRef>& x,
+                                            const std::pair<uint64_t, RowRef>& y) {
+      return x.first < y.first;
+    });
+    ntt_ragged_s::Gang gg;
+    gg.cls = std::get<0>(kv.first);
+    gg.log_n = std::get<1>(kv.first);
+    gg.inv = std::get<2>(kv.first);
+    gg.off = (uint32_t)table.size();
+    gg.n = (uint32_t)v.size();
+    for (const auto& x : v) table.push_back(x.second);
+    r->gangs.push_back(gg);
+  }
   r->n_items[0] = (uint32_t)narrow.size();
   r->n_items[1] = (uint32_t)wide.size();
   r->items = narrow;
@@ -335,6 +510,11 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
     e = hipMemcpy(r->d_jobs, r->jobs.data(), sizeof(RaggedJobDev) * r->jobs.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !r->items.empty())
     e = hipMemcpy(r->d_items, r->items.data(), sizeof(RaggedItem) * r->items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !table.empty()) {
+    e = hipMalloc(&r->d_rows, sizeof(RowRef) * table.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(r->d_rows, table.data(), sizeof(RowRef) * table.size(), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     free_ragged(r);
     return hip_fail(e, "ragged descriptors");
@@ -356,13 +536,19 @@ ntt_status ntt_ragged_run(ntt_ragged_t r, void* stream) {
     hipStream_t cap = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    // one capture branch per group of large transforms (at most 8)
+    std::vector<hipStream_t> branches(std::min<size_t>(8, r->gangs.size()), nullptr);
+    for (auto& b : branches)
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = launch_all(r, cap, false);
+      hipError_t le = launch_all(r, cap, false, &branches);
       e = hipStreamEndCapture(cap, &r->graph);
       if (le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+    for (hipStream_t b : branches)
+      if (b) (void)hipStreamDestroy(b);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return hip_fail(e, "ragged graph capture");
   }
@@ -372,7 +558,9 @@ ntt_status ntt_ragged_run(ntt_ragged_t r, void* stream) {
 
 ntt_status ntt_ragged_info(ntt_ragged_t r, uint32_t* items, uint32_t* workgroups) {
   if (!r) return fail(NTT_EINVAL, "null ragged batch");
-  if (items) *items = r->n_items[0] + r->n_items[1];
+  uint32_t rows = 0;
+  for (const auto& gg : r->gangs) rows += gg.n;
+  if (items) *items = r->n_items[0] + r->n_items[1] + rows;
   if (workgroups) *workgroups = (r->n_items[0] ? r->grid[0] : 0) + (r->n_items[1] ? r->grid[1] : 0);
   return NTT_OK;
 }

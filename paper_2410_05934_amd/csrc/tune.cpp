@@ -317,8 +317,9 @@ ntt_status ntt_tune_ragged(uint32_t N, const uint64_t* moduli, uint32_t num_modu
   for (uint32_t rl : {11u, 12u}) {
     ntt_job jobs[2] = {{p, NTT_OP_FORWARD, batch, buf}, {p, NTT_OP_INVERSE, batch, buf}};
     ntt_ragged_t rf = nullptr, ri = nullptr;
-    st = ntt_ragged_create(&rf, &jobs[0], 1, NTT_RAGGED_NO_GRAPH | NTT_RAGGED_ROW_LOG(rl));
-    if (st == NTT_OK) st = ntt_ragged_create(&ri, &jobs[1], 1, NTT_RAGGED_NO_GRAPH | NTT_RAGGED_ROW_LOG(rl));
+    const uint32_t fl = NTT_RAGGED_NO_GRAPH | NTT_RAGGED_IN_WORKGROUP | NTT_RAGGED_ROW_LOG(rl);
+    st = ntt_ragged_create(&rf, &jobs[0], 1, fl);
+    if (st == NTT_OK) st = ntt_ragged_create(&ri, &jobs[1], 1, fl);
     if (st != NTT_OK) {
       if (rf) ntt_ragged_destroy(rf);
       break;

@@ -62,8 +62,10 @@ def _check(specs, jobs, want):
         assert np.array_equal(to_host(t, wb).astype(np.uint64), w), (N, mods, wb, batch, op)
 
 
-@pytest.mark.parametrize("flags", [0, ntt.RAGGED_NO_GRAPH, ntt.ragged_row_log(11),
-                                   ntt.ragged_row_log(12) | ntt.RAGGED_NO_GRAPH])
+@pytest.mark.parametrize("flags", [0, ntt.RAGGED_NO_GRAPH,
+                                   ntt.RAGGED_IN_WORKGROUP,
+                                   ntt.RAGGED_IN_WORKGROUP | ntt.ragged_row_log(11),
+                                   ntt.RAGGED_IN_WORKGROUP | ntt.ragged_row_log(12) | ntt.RAGGED_NO_GRAPH])
 def test_ragged_mixed_sizes_classes_widths(flags):
     specs = _mixed_jobs(1)
     jobs, hosts = _build(specs, 1)
