@@ -271,6 +271,7 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
     x1 = to_device(synth.uniform_poly(7, [q1], 1, N), 32)
     t1 = _time(torch, lambda: (p1.forward(x1, stream), p1.inverse(x1, stream)), 200, stream)
     out["c1_fwd_inv_us"] = round(t1 * 1e3, 2)
+    out["single_polynomial_56bit"] = run_latency(args, torch, ntt, synth, to_device, stream)
     if not args.no_ragged:
         out["c4_ragged"] = run_ragged(args, torch, ntt, synth, to_device, stream)
     if not args.no_serving:
@@ -286,6 +287,36 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
             "batched": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["batched"]["open_loop"]],
             "serial": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["serial"]["open_loop"]],
         }
+    return out
+
+
+def run_latency(args, torch, ntt, synth, to_device, stream):
+    """One polynomial over one 56-bit prime, N = 2^12 .. 2^16 (the single-transform
+    setting of the paper's Tab. ntt-mix, Sec. VI-A): the forward time at every pass
+    split (the paper's switching-point sweep, Sec. V-C), then the forward and inverse
+    with the split and row radix the autotuner picks for this shape.  Times are
+    means over back-to-back calls on one stream."""
+    q = synth.latency_prime()
+    out = {"q_bits": q.bit_length(), "reps": 200}
+    for logn in (args.latency_logn or range(12, 17)):
+        N = 1 << logn
+        x = to_device(synth.uniform_poly(900 + logn, [q], 1, N), 64)
+        sweep = {}
+        for n1 in range(0, 6):
+            if not ((n1 == 0 and logn <= 14) or (n1 >= 1 and 4 <= logn - n1 <= 14)):
+                continue
+            p = ntt.Plan(N, [q], 64, flags=ntt.flag_split(n1))
+            sweep[str(n1)] = round(_time(torch, lambda: p.forward(x, stream), 200, stream) * 1e3, 2)
+            p.close()
+        if not args.no_tune:
+            ntt.tune_split(N, [q], 64, 1)
+        p = ntt.Plan(N, [q], 64)
+        fwd = _time(torch, lambda: p.forward(x, stream), 200, stream) * 1e3
+        inv = _time(torch, lambda: p.inverse(x, stream), 200, stream) * 1e3
+        out[f"N=2^{logn}"] = {"split_sweep_fwd_us": sweep, "split": p.split_for(1),
+                              "fwd_us": round(fwd, 2), "inv_us": round(inv, 2)}
+        p.close()
+    _log(f"[bench] single polynomial, 56-bit q: {out}")
     return out
 
 
@@ -402,9 +433,22 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--latency-only", action="store_true",
+                    help="only run the single-polynomial 56-bit section (one JSON line) and exit")
+    ap.add_argument("--latency-logn", type=int, nargs="*", default=None,
+                    help="log2 N of the single-polynomial section (default 12 .. 16)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.latency_only:
+        import torch
+        import paper_2410_05934_amd as ntt
+        from paper_2410_05934_amd import synth
+        from paper_2410_05934_amd.tensors import to_device
+        torch.cuda.init()
+        res = run_latency(args, torch, ntt, synth, to_device, torch.cuda.current_stream())
+        print(json.dumps({"single_polynomial_56bit": res}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (every "

@@ -69,8 +69,10 @@ typedef enum {
 #define NTT_FLAG_FORCE_INT64 (1u << 16)
 /* Row passes of 2^10 .. 2^13 words with 8 values per thread (radix-8 rounds,
  * twice the threads of radix-16 rounds, one more LDS exchange).  Without it the
- * tuning table chooses per direction and shape, else radix-8 for inverse rows
- * and single-pass polymul rows, radix-16 for forward and two-pass polymul rows. */
+ * tuning table chooses per direction and shape, else: radix-4 rows (below) for
+ * the 64-bit integer class (q >= 2^50) when a call has at most 256 row chunks
+ * (one per compute unit); otherwise radix-8 for inverse rows, forward rows of
+ * 2^10 .. 2^11 words and single-pass polymul rows, radix-16 for the rest. */
 #define NTT_FLAG_ROW_RADIX8 (1u << 17)
 /* Two-pass transforms with 2^12-word rows (N = 2^13 .. 2^16) run both passes in
  * one persistent launch: the one global synchronisation per transform of the
@@ -82,6 +84,13 @@ typedef enum {
  * slower than the default two launches (cross-XCD release/acquire per piece);
  * it is there for callers that need a single launch per call. */
 #define NTT_FLAG_FUSED (1u << 18)
+/* Forward and inverse row passes of 2^8 .. 2^12 words with 4 values per thread
+ * (radix-4 rounds: four times the threads of radix-16 rounds and twice the LDS
+ * exchanges).  It shortens each thread's chain of dependent butterflies, which
+ * is what bounds a call with few transforms (the single-polynomial latency
+ * regime of the paper's Tab. ntt-mix); polymul rows ignore it.  Exclusive with
+ * NTT_FLAG_ROW_RADIX8. */
+#define NTT_FLAG_ROW_RADIX4 (1u << 19)
 
 /* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
  * precomputed per modulus as the paper keeps them in constant memory, Sec. II-E).

@@ -16,7 +16,7 @@ import os
 import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
-           "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_FUSED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
+           "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_ROW_RADIX4", "FLAG_FUSED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
            "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
            "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
            "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
@@ -30,6 +30,7 @@ _lib = None
 FLAG_FORCE_INT64 = 1 << 16
 FLAG_ROW_RADIX8 = 1 << 17
 FLAG_FUSED = 1 << 18
+FLAG_ROW_RADIX4 = 1 << 19
 
 STATUS = {0: "NTT_OK", 1: "NTT_EINVAL", 2: "NTT_ENOTPRIME", 3: "NTT_ENOROOT", 4: "NTT_ERANGE",
           5: "NTT_ENOMEM", 6: "NTT_EDEVICE", 7: "NTT_EBUSY", 8: "NTT_ETIMEOUT"}

@@ -83,9 +83,11 @@ uint32_t tuned_split_for(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t f
 uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback);
 bool split_valid(int log_n, int n1);
 
-// Values per thread (log2) of row passes: forced by NTT_FLAG_ROW_RADIX8, else the
-// tuning table, else radix-8 for inverse rows and single-pass polymul rows of
-// 2^10..2^13 words and radix-16 for forward rows and two-pass polymul rows.
+// Values per thread (log2) of row passes: forced by NTT_FLAG_ROW_RADIX8 or
+// NTT_FLAG_ROW_RADIX4, else the tuning table, else radix-4 for forward and
+// inverse rows of calls in the 64-bit integer class with at most kLatencyChunks
+// row chunks, radix-8 for inverse rows, forward rows of 2^10..2^11 words and
+// single-pass polymul rows, and radix-16 for the rest.
 uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback);
 inline int dominant_class(const ntt_plan_s* p) {
   uint32_t best = 0, cnt = 0;
@@ -93,23 +95,42 @@ inline int dominant_class(const ntt_plan_s* p) {
     if (p->cls_cnt[c] > cnt) { cnt = p->cls_cnt[c]; best = c; }
   return (int)best;
 }
+// Row lengths each radix is built for: radix-16 2^4..2^14, radix-8 2^10..2^13,
+// radix-4 2^8..2^12 (at most 1024 threads per chunk).
+inline bool row_rb_ok(int rb, int n2) {
+  if (rb == 4) return n2 >= 4 && n2 <= 14;
+  if (rb == 3) return n2 >= 10 && n2 <= 13;
+  if (rb == 2) return n2 >= 8 && n2 <= 12;
+  return false;
+}
+// Up to one row chunk per compute unit, a thread's chain of dependent
+// butterflies bounds the pass, not the work per compute unit.  That matters for
+// the integer class, whose butterfly is several times longer than the fp64
+// ones (measured on one 56-bit prime: N = 2^12 forward 10.3 us with radix-16
+// rows, 7.0 us with radix-4; fp64 classes gain nothing).
+constexpr uint64_t kLatencyChunks = 256;
 inline int row_rb_for(const ntt_plan_s* p, bool inv, uint32_t split, uint32_t batch) {
   const int n2 = (int)p->log_n - (int)split;
-  if (n2 < 10 || n2 > 13) return 4;
-  if (p->row_rb) return p->row_rb;
-  const uint32_t fallback = inv ? 3u : 4u;
-  return (int)tuned_row_rb(inv ? 3u : 2u, p->log_n, (uint32_t)dominant_class(p),
-                           (uint64_t)batch * p->L, fallback);
+  if (p->row_rb) return row_rb_ok(p->row_rb, n2) ? p->row_rb : 4;
+  const uint64_t chunks = ((uint64_t)batch * p->L) << split;
+  const int cls = dominant_class(p);
+  uint32_t fallback = 4;
+  if (cls == 2 && chunks <= kLatencyChunks && row_rb_ok(2, n2)) fallback = 2;
+  else if ((inv || n2 <= 11) && row_rb_ok(3, n2)) fallback = 3;
+  const int rb = (int)tuned_row_rb(inv ? 3u : 2u, p->log_n, (uint32_t)cls, (uint64_t)batch * p->L,
+                                   fallback);
+  return row_rb_ok(rb, n2) ? rb : 4;
 }
 
 inline int polymul_rb_for(const ntt_plan_s* p, uint32_t split, uint32_t batch) {
   const int n2 = (int)p->log_n - (int)split;
-  if (n2 < 10 || n2 > 13) return 4;
-  if (p->row_rb) return p->row_rb;
+  if (!row_rb_ok(3, n2)) return 4;
+  if (p->row_rb == 3 || p->row_rb == 4) return p->row_rb;
   // measured on 2 x 36 x 2^16: radix-16 rows 46 us, radix-8 52 us (two-pass)
   const uint32_t fallback = split ? 4u : 3u;
-  return (int)tuned_row_rb(4u, p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L,
-                           fallback);
+  const int rb = (int)tuned_row_rb(4u, p->log_n, (uint32_t)dominant_class(p),
+                                   (uint64_t)batch * p->L, fallback);
+  return rb == 3 ? 3 : 4;
 }
 
 // Single-launch two-pass form (both passes in one persistent launch): for

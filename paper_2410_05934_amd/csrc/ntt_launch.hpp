@@ -19,7 +19,8 @@ template <class A, int LOGN2, bool INV, bool TWO, int RB = 4>
 hipError_t launch_row_n(const RowArgs& a, hipStream_t s) {
   using S = RowShape<LOGN2, RB>;
   const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
-  LaunchTimer t(RB == 4 ? "row" : "row8", A::kName, LOGN2, INV, TWO, (uint64_t)a.total_chunks << LOGN2, s);
+  LaunchTimer t(RB == 4 ? "row" : RB == 3 ? "row8" : "row4", A::kName, LOGN2, INV, TWO,
+                (uint64_t)a.total_chunks << LOGN2, s);
   hipLaunchKernelGGL((row_kernel<A, LOGN2, INV, TWO, RB>), dim3(blocks), dim3(S::BLOCK), 0, s, a);
   return hipGetLastError();
 }
@@ -45,6 +46,16 @@ hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
 
 template <class A, bool INV, bool TWO>
 hipError_t launch_row(int logn2, const RowArgs& a, hipStream_t s, int rb = 4) {
+  if (rb == 2) {
+    switch (logn2) {
+      case 8: return launch_row_n<A, 8, INV, TWO, 2>(a, s);
+      case 9: return launch_row_n<A, 9, INV, TWO, 2>(a, s);
+      case 10: return launch_row_n<A, 10, INV, TWO, 2>(a, s);
+      case 11: return launch_row_n<A, 11, INV, TWO, 2>(a, s);
+      case 12: return launch_row_n<A, 12, INV, TWO, 2>(a, s);
+      default: break;
+    }
+  }
   if (rb == 3) {
     switch (logn2) {
       case 10: return launch_row_n<A, 10, INV, TWO, 3>(a, s);

@@ -290,6 +290,8 @@ ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* moduli,
     ntt_status st = check_modulus(N, moduli[l], word_bits);
     if (st != NTT_OK) return st;
   }
+  if ((flags & NTT_FLAG_ROW_RADIX8) && (flags & NTT_FLAG_ROW_RADIX4))
+    return fail(NTT_EINVAL, "NTT_FLAG_ROW_RADIX8 and NTT_FLAG_ROW_RADIX4 are exclusive");
   const int log_n = ilog2(N);
   uint32_t n1 = default_split(log_n);
   if (flags & NTT_FLAG_SPLIT_MASK) {
@@ -310,7 +312,7 @@ ntt_status ntt_plan_create(ntt_plan_t* out, uint32_t N, const uint64_t* moduli,
   p->flags = flags;
   p->log_n1 = n1;
   p->forced_split = (flags & NTT_FLAG_SPLIT_MASK) ? (int)n1 : -1;
-  p->row_rb = (flags & NTT_FLAG_ROW_RADIX8) ? 3 : 0;
+  p->row_rb = (flags & NTT_FLAG_ROW_RADIX8) ? 3 : (flags & NTT_FLAG_ROW_RADIX4) ? 2 : 0;
   p->moduli.assign(moduli, moduli + num_moduli);
   p->psi.resize(num_moduli);
   p->cls.resize(num_moduli);

@@ -130,7 +130,7 @@ uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows
       const int bb = (int)b + sgn * d;
       if (bb < 0) continue;
       auto it = g_table.find(Key(kind, log_n, cls, (uint32_t)bb));
-      if (it != g_table.end() && (it->second.value == 3 || it->second.value == 4))
+      if (it != g_table.end() && it->second.value >= 2 && it->second.value <= 4)
         return it->second.value;
       if (d == 0) break;
     }
@@ -205,13 +205,12 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
     const int n2 = log_n - n1;
     float bf = 1e30f, bi = 1e30f;
     uint32_t rf = 4, ri = 4;
-    for (int rb : {4, 3}) {
-      if (rb == 3 && (n2 < 10 || n2 > 13)) continue;
+    for (int rb : {4, 3, 2}) {
+      if (rb != 4 && !row_rb_ok(rb, n2)) continue;  // radix-16 also stands for "no row pass"
       ntt_plan_t p = nullptr;
-      st = ntt_plan_create(&p, N, moduli, num_moduli, word_bits,
-                           NTT_FLAG_SPLIT(n1) | (rb == 3 ? NTT_FLAG_ROW_RADIX8 : 0u));
+      st = ntt_plan_create(&p, N, moduli, num_moduli, word_bits, NTT_FLAG_SPLIT(n1));
       if (st != NTT_OK) break;
-      if (rb == 4) p->row_rb = 4;  // pin radix-16 for this measurement
+      p->row_rb = rb;  // pin the radix for this measurement
       float uf = 0, ui = 0;
       st = time_dir(p, false, &uf);
       if (st == NTT_OK) st = time_dir(p, true, &ui);

@@ -139,6 +139,12 @@ def c3_prime() -> int:
     return primes_below(1 << 32, 1 << 11, 1)[0]
 
 
+def latency_prime() -> int:
+    """The largest prime q = 1 mod 2^17 below 2^56: one 56-bit modulus, the width the
+    paper's single-transform measurements use (Sec. VI-A), admissible for every N <= 2^16."""
+    return primes_below(1 << 56, 1 << 17, 1)[0]
+
+
 def c4_pool(seed: int, size: int = 64) -> list[int]:
     """`size` distinct primes q = 1 mod 2^17, widths uniform in 30..60 bits."""
     pool: list[int] = []

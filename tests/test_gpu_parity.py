@@ -257,6 +257,96 @@ def test_radix8_rows_are_bit_identical(cls, logn):
     assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
 
 
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64", "mixed64"])
+@pytest.mark.parametrize("logn", [8, 10, 12, 13, 16])
+def test_radix4_rows_are_bit_identical(cls, logn):
+    """Row passes with 4 values per thread (radix-4 rounds), forced for every split
+    whose row part is 2^8 .. 2^12 words, give the oracle's words in both directions;
+    polymul under the same flag keeps its own rows and stays exact."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    a = _data(300 + logn, moduli, 3, N, word_bits)
+    b = _data(301 + logn, moduli, 3, N, word_bits)
+    want_f = oracle.forward(a, moduli)
+    want_i = oracle.inverse(a, moduli)
+    splits = [n1 for n1 in _valid_splits(logn) if 8 <= logn - n1 <= 12]
+    assert splits
+    for n1 in splits:
+        plan = ntt.Plan(N, moduli, word_bits, flags=ntt.flag_split(n1) | ntt.FLAG_ROW_RADIX4)
+        assert np.array_equal(_run_fwd(plan, a, word_bits), want_f), n1
+        assert np.array_equal(_run_inv(plan, a, word_bits), want_i), n1
+    da, db = to_device(a, word_bits), to_device(b, word_bits)
+    out = empty_device(a.shape, word_bits)
+    ntt.Plan(N, moduli, word_bits, flags=ntt.FLAG_ROW_RADIX4).polymul(out, da, db)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
+
+
+Q56 = synth.latency_prime()
+
+
+@pytest.mark.parametrize("logn", [10, 12, 13, 14, 15, 16])
+def test_single_polynomial_56_bit_prime_uses_radix4_rows(logn):
+    """One polynomial over one 56-bit prime (the paper's single-transform setting):
+    the default plan runs radix-4 rows (few row chunks) and matches the oracle."""
+    N = 1 << logn
+    a = _data(500 + logn, [Q56], 1, N, 64)
+    b = _data(501 + logn, [Q56], 1, N, 64)
+    plan = ntt.Plan(N, [Q56], 64)
+    assert plan.limb_class(0) == 2  # the 64-bit integer class
+    ntt.stats_reset()
+    ntt.stats_enable(True)
+    try:
+        f = _run_fwd(plan, a, 64)
+        i = _run_inv(plan, a, 64)
+        names = set(ntt.stats_collect())
+    finally:
+        ntt.stats_enable(False)
+        ntt.stats_reset()
+    assert np.array_equal(f, oracle.forward(a, [Q56]))
+    assert np.array_equal(i, oracle.inverse(a, [Q56]))
+    n2 = logn - plan.split_for(1)
+    if 8 <= n2 <= 12:
+        assert any(k.startswith("row4_fwd_i64") for k in names), names
+        assert any(k.startswith("row4_inv_i64") for k in names), names
+    da, db = to_device(a, 64), to_device(b, 64)
+    out = empty_device(a.shape, 64)
+    plan.polymul(out, da, db)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out, 64).astype(np.uint64), oracle.polymul(a, b, [Q56]))
+
+
+@pytest.mark.parametrize("cls", ["u32", "i64"])
+@pytest.mark.parametrize("logn", [10, 12, 16])
+def test_tuning_table_radix4_rows_are_bit_identical(cls, logn, tmp_path):
+    """A tuning table that picks 4 values per row-pass thread for forward and
+    inverse rows (and, invalidly, for polymul rows, which keep radix-8/16) gives
+    the oracle's words at a batch far above the radix-4 default."""
+    import json
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    entries = [{"kind": k, "log_n": logn, "cls": c, "bucket": bk, "value": 2}
+               for k in (2, 3, 4) for c in range(3) for bk in range(25)]
+    path = tmp_path / "rb4.json"
+    path.write_text(json.dumps({"entries": entries}))
+    ntt.tune_clear()
+    ntt.tune_load(str(path))
+    try:
+        batch = 150
+        a = _data(93 + logn, moduli, batch, N, word_bits)
+        b = _data(94 + logn, moduli, batch, N, word_bits)
+        plan = ntt.Plan(N, moduli, word_bits)
+        assert np.array_equal(_run_fwd(plan, a, word_bits), oracle.forward(a, moduli))
+        assert np.array_equal(_run_inv(plan, a, word_bits), oracle.inverse(a, moduli))
+        da, db = to_device(a, word_bits), to_device(b, word_bits)
+        out = empty_device(a.shape, word_bits)
+        plan.polymul(out, da, db)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
+    finally:
+        ntt.tune_clear()
+
+
 @pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
 @pytest.mark.parametrize("logn", [10, 13, 16])
 def test_tuning_table_radix16_rows_are_bit_identical(cls, logn, tmp_path):
