@@ -39,6 +39,7 @@ struct ntt_plan_s {
   std::vector<nttk::LimbDev> h_limbs; // host copy of the same constants
   std::vector<const nttk::PrimeTable*> tables;  // shared tables, one per limb
   uint32_t* d_cls_limbs = nullptr;    // device limb lists, concatenated per class
+  std::vector<uint32_t> h_cls_limbs;  // host copy of the same lists
   uint32_t cls_off[3] = {0, 0, 0};
   uint32_t cls_cnt[3] = {0, 0, 0};
 };

@@ -57,6 +57,11 @@ struct RowArgs {
   uint32_t log_n1;           // column stages before this pass (0: single pass)
   uint32_t total_chunks;     // batch * n_cls * N1
   uint32_t batch;            // polynomials
+  // When the launch's class holds one limb (n_cls == 1): that limb's index and
+  // constants, so that short launches read them from their arguments instead of
+  // through two dependent global loads (limb list, then constants).
+  uint32_t limb0;
+  LimbDev one;
 };
 
 struct ColArgs {
@@ -71,6 +76,8 @@ struct ColArgs {
   uint32_t total_cols;       // batch * n_cls * N2
   void* dst2;                // optional second operand of the same shape (polymul's b):
   const void* src2;          //   threads total_cols .. 2*total_cols-1 take it
+  uint32_t limb0;            // n_cls == 1: the limb and its constants (as in RowArgs)
+  LimbDev one;
 };
 
 struct EltArgs {
@@ -421,6 +428,8 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
   return (b % kXcds) * per + b / kXcds;
 }
 
+// ONE: the launch's class holds one limb, given in the arguments (a.limb0).
+template <bool ONE = false>
 __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int log_n2) {
   ChunkPos p;
   p.valid = gc < a.total_chunks;
@@ -430,7 +439,7 @@ __device__ __forceinline__ ChunkPos chunk_pos(const RowArgs& a, uint32_t gc, int
   const uint32_t rest = g / a.batch;
   const uint32_t c = rest & (n1 - 1);
   const uint32_t li = rest >> a.log_n1;
-  p.limb = a.cls_limbs[li];
+  p.limb = ONE ? a.limb0 : a.cls_limbs[li];
   p.off = ((uint64_t)poly * a.L + p.limb) << a.log_n;
   p.off += (uint64_t)c << log_n2;
   p.base = n1 + c;
@@ -542,7 +551,20 @@ row_kernel(RowArgs args) {
   __shared__ V lds_all[S::LDS_ELEMS];
   const uint32_t ci = S::CPW == 1 ? 0u : threadIdx.x / S::TPC;
   const uint32_t tt = threadIdx.x & (S::TPC - 1);
-  const ChunkPos cp = chunk_pos(args, xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci, LOGN2);
+  const uint32_t gc = xcd_block(blockIdx.x, gridDim.x) * S::CPW + ci;
+  if constexpr (RB == 2) {
+    // Radix-4 rows serve short launches, where the dependent loads of the limb
+    // list and constants are a visible part of the launch: one limb comes from
+    // the arguments.
+    if (args.n_cls == 1) {
+      const ChunkPos cp = chunk_pos<true>(args, gc, LOGN2);
+      row_chunk<A, LOGN2, INV, TWO_PASS, RB>(reinterpret_cast<W*>(args.dst) + cp.off,
+                                         reinterpret_cast<const W*>(args.src) + cp.off, args.one,
+                                         cp.base, tt, lds_all + ci * S::CHUNK_LDS, cp.valid);
+      return;
+    }
+  }
+  const ChunkPos cp = chunk_pos(args, gc, LOGN2);
   row_chunk<A, LOGN2, INV, TWO_PASS, RB>(reinterpret_cast<W*>(args.dst) + cp.off,
                                      reinterpret_cast<const W*>(args.src) + cp.off,
                                      args.limbs[cp.limb], cp.base, tt,
@@ -681,7 +703,9 @@ __device__ __forceinline__ void col_one(typename A::W* __restrict__ dst,
   }
 }
 
-template <class A, int LOGN1, bool INV, bool TWO_PASS>
+// ONE: the launch's class holds one limb (n_cls == 1), whose index and constants
+// come from the arguments; its twiddles are then wave-uniform loads.
+template <class A, int LOGN1, bool INV, bool TWO_PASS, bool ONE = false>
 __global__ void __launch_bounds__(kColBlock)
 col_kernel(ColArgs args) {
   using W = typename A::W;
@@ -698,13 +722,20 @@ col_kernel(ColArgs args) {
   const uint32_t n2 = 1u << args.log_n2;
   const uint32_t r = g & (n2 - 1);
   const uint32_t rest = g >> args.log_n2;
-  const uint32_t li = rest % args.n_cls;
-  const uint32_t poly = rest / args.n_cls;
-  const uint32_t limb = args.cls_limbs[li];
-  const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
-  col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(dst_base) + off,
-                                   reinterpret_cast<const W*>(src_base) + off, args.limbs[limb],
-                                   args.log_n2, valid);
+  if constexpr (ONE) {
+    const uint64_t off = (((uint64_t)rest * args.L + args.limb0) << args.log_n) + r;
+    col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(dst_base) + off,
+                                     reinterpret_cast<const W*>(src_base) + off, args.one,
+                                     args.log_n2, valid);
+  } else {
+    const uint32_t li = rest % args.n_cls;
+    const uint32_t poly = rest / args.n_cls;
+    const uint32_t limb = args.cls_limbs[li];
+    const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
+    col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(dst_base) + off,
+                                     reinterpret_cast<const W*>(src_base) + off, args.limbs[limb],
+                                     args.log_n2, valid);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -40,7 +40,10 @@ hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
   const uint64_t threads = (uint64_t)a.total_cols * (a.src2 ? 2 : 1);
   const uint32_t blocks = (uint32_t)((threads + kColBlock - 1) / kColBlock);
   LaunchTimer t("col", A::kName, LOGN1, INV, TWO, threads << LOGN1, s);
-  hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(kColBlock), 0, s, a);
+  if (a.n_cls == 1)
+    hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO, true>), dim3(blocks), dim3(kColBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(kColBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -134,6 +137,8 @@ inline RowArgs row_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.log_n1 = (uint32_t)n1;
   a.total_chunks = batch * p->cls_cnt[c] << n1;
   a.batch = batch;
+  a.limb0 = p->cls_cnt[c] == 1 ? p->h_cls_limbs[p->cls_off[c]] : 0u;
+  a.one = p->h_limbs[a.limb0];
   return a;
 }
 
@@ -152,6 +157,8 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.total_cols = (batch * p->cls_cnt[c]) << a.log_n2;
   a.dst2 = nullptr;
   a.src2 = nullptr;
+  a.limb0 = p->cls_cnt[c] == 1 ? p->h_cls_limbs[p->cls_off[c]] : 0u;
+  a.one = p->h_limbs[a.limb0];
   return a;
 }
 

@@ -142,6 +142,7 @@ static ntt_status build_plan(ntt_plan_s* p, const uint64_t* moduli) {
   e = hipMemcpy(p->d_cls_limbs, lists.data(), sizeof(uint32_t) * lists.size(),
                 hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(limb lists)");
+  p->h_cls_limbs = lists;
   return NTT_OK;
 }
 
