@@ -62,6 +62,7 @@ def _load():
                 "orc_pointwise_mul": (None, [_u64p, _u64p, _u64p, u64, u64]),
                 "orc_mac": (None, [_u64p, ctypes.POINTER(_u64p), ctypes.POINTER(_u64p), u32, u64, u64]),
                 "orc_polymul": (i32, [_u64p, _u64p, _u64p, u32, u64]),
+                "orc_automorph": (None, [_u64p, _u64p, u32, u64, u64]),
                 "orc_forward_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
                 "orc_inverse_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
                 "orc_num_cores": (i32, []),
@@ -222,3 +223,29 @@ def polymul(a, b, moduli, nthreads: int = 0) -> np.ndarray:
     fa = forward(a, moduli, nthreads)
     fb = forward(b, moduli, nthreads)
     return inverse(pointwise_mul(fa, fb, moduli), moduli, nthreads)
+
+
+# -- automorphisms (Sec. III, Sec. IV-B) --------------------------------------
+
+def automorph(a, moduli, k: int) -> np.ndarray:
+    """sigma_k on data[..., L, N] in the coefficient domain: b(x) = a(x^k) in
+    Z_q[x]/(x^N+1) per limb, k odd (the plain substitution, term by term)."""
+    x = _u64(a)
+    mod = _u64(np.atleast_1d(moduli))
+    N, L = x.shape[-1], mod.shape[0]
+    xr = x.reshape(-1, L, N)
+    out = np.empty_like(xr)
+    lib = _load()
+    for p in range(xr.shape[0]):
+        for l in range(L):
+            src = np.ascontiguousarray(xr[p, l])
+            dst = np.empty(N, dtype=np.uint64)
+            lib.orc_automorph(_p(dst), _p(src), N, int(mod[l]), int(k))
+            out[p, l] = dst
+    return out.reshape(x.shape)
+
+
+def automorph_transformed(ahat, moduli, k: int) -> np.ndarray:
+    """sigma_k on transformed data (the forward transform's output order): the
+    transform of sigma_k applied to the polynomial whose transform is ahat."""
+    return forward(automorph(inverse(ahat, moduli), moduli, k), moduli)

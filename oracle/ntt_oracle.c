@@ -259,6 +259,22 @@ int orc_polymul(uint64_t* c, const uint64_t* a, const uint64_t* b, uint32_t N, u
   return rc;
 }
 
+/* Automorphism sigma_k of R_q = Z_q[x]/(x^N+1) (Sec. III lists Automorph among
+ * the CKKS operators; Sec. IV-B builds repacking on it): b(x) = a(x^k) for odd
+ * k.  Written as the substitution itself: the term a_i x^i becomes a_i x^(i k);
+ * the exponent is reduced mod 2N because x^(2N) = 1, and x^N = -1 turns an
+ * exponent e >= N into -x^(e-N).  Every term is added into b, so nothing here
+ * assumes the map is a permutation. */
+void orc_automorph(uint64_t* b, const uint64_t* a, uint32_t N, uint64_t q, uint64_t k) {
+  const uint64_t two_n = 2 * (uint64_t)N;
+  for (uint32_t t = 0; t < N; ++t) b[t] = 0;
+  for (uint32_t i = 0; i < N; ++i) {
+    const uint64_t e = (uint64_t)(((u128)i * k) % two_n);
+    if (e < N) b[e] = addm(b[e], a[i], q);
+    else b[e - N] = subm(b[e - N], a[i], q);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Batched drivers: data[batch][L][N], moduli[L].  Independent (poly, limb)
  * rows are handed to a pool of threads; each row is transformed by the same

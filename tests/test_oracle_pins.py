@@ -243,3 +243,93 @@ def test_batched_layout_rows_use_their_own_modulus():
     for p in range(2):
         for l, q in enumerate(qs):
             assert (f[p, l] == oracle.forward(data[p, l], [q], nthreads=1)).all()
+
+
+# -- automorphisms ----------------------------------------------------------------
+
+AUTO_PRIMES = [7681, 4294957057, 1125899903827969, 4611686018425815041]
+
+
+def _root_2n(N, q):
+    """A primitive 2N-th root of unity found by brute force (not the oracle's psi)."""
+    for g in range(2, 1000):
+        r = pow(g, (q - 1) // (2 * N), q)
+        if pow(r, N, q) == q - 1:
+            return r
+    raise AssertionError("no root found")
+
+
+def _horner(a, z, q):
+    acc = 0
+    for c in reversed(a):
+        acc = (acc * z + int(c)) % q
+    return acc
+
+
+@pytest.mark.parametrize("q", AUTO_PRIMES)
+def test_automorph_evaluates_at_kth_powers(q):
+    """sigma_k(a) at every root z of x^N + 1 equals a at z^k (Horner, big integers)."""
+    N = 64
+    a = np.array(_rand(q, N, 21), dtype=np.uint64)
+    r = _root_2n(N, q)
+    for k in [3, 5, 2 * N - 1, 77]:
+        b = oracle.automorph(a, [q], k)
+        for j in range(0, 2 * N, 2):
+            z = pow(r, j + 1, q)  # the odd powers of r are the N roots of x^N + 1
+            assert _horner(b, z, q) == _horner(a, pow(z, k, q), q), (k, j)
+
+
+@pytest.mark.parametrize("q", AUTO_PRIMES[:2])
+def test_automorph_composes_and_has_the_order_of_k(q):
+    N = 128
+    a = np.array(_rand(q, N, 22), dtype=np.uint64)
+    for k1, k2 in [(3, 5), (5, 5), (2 * N - 1, 7), (101, 55)]:
+        lhs = oracle.automorph(oracle.automorph(a, [q], k2), [q], k1)
+        assert np.array_equal(lhs, oracle.automorph(a, [q], (k1 * k2) % (2 * N)))
+    # 5 generates a cyclic subgroup of order N/2 in the units mod 2N
+    b = a.copy()
+    for _ in range(N // 2):
+        b = oracle.automorph(b, [q], 5)
+    assert np.array_equal(b, a)
+    assert np.array_equal(oracle.automorph(a, [q], 1), a)
+
+
+@pytest.mark.parametrize("q", AUTO_PRIMES)
+def test_automorph_conjugation_closed_form(q):
+    """k = 2N - 1 maps x^i to x^(-i) = -x^(N-i): b_0 = a_0, b_t = -a_(N-t)."""
+    N = 32
+    a = _rand(q, N, 23)
+    b = [int(x) for x in oracle.automorph(np.array(a, dtype=np.uint64), [q], 2 * N - 1)]
+    assert b[0] == a[0]
+    assert all(b[t] == (q - a[N - t]) % q for t in range(1, N))
+
+
+@pytest.mark.parametrize("q", AUTO_PRIMES[1:])
+def test_automorph_is_a_ring_homomorphism(q):
+    N = 32
+    a = _rand(q, N, 24)
+    b = _rand(q, N, 25)
+    ab = py_ref.negacyclic_schoolbook(a, b, q)
+    for k in [3, 5, 61]:
+        sa = [int(x) for x in oracle.automorph(np.array(a, dtype=np.uint64), [q], k)]
+        sb = [int(x) for x in oracle.automorph(np.array(b, dtype=np.uint64), [q], k)]
+        sab = [int(x) for x in oracle.automorph(np.array(ab, dtype=np.uint64), [q], k)]
+        assert sab == py_ref.negacyclic_schoolbook(sa, sb, q)
+
+
+@pytest.mark.parametrize("q", AUTO_PRIMES[1:])
+def test_automorph_transformed_permutes_slots(q):
+    """In the transform domain sigma_k only moves slots: forward(sigma_k(x)) holds
+    the values r^((2 brv(j) + 1) k), a rearrangement of forward(x)."""
+    N = 256
+    psi = oracle.psi(N, q)
+    x = np.zeros(N, dtype=np.uint64)
+    x[1] = 1
+    fx = oracle.forward(x, [q])
+    for k in [3, 5, 2 * N - 1]:
+        g = [int(v) for v in oracle.automorph_transformed(fx, [q], k)]
+        assert g == [pow(psi, (2 * py_ref.brv(j, 8) + 1) * k, q) for j in range(N)]
+        assert sorted(g) == sorted(int(v) for v in fx)
+    a = np.array(_rand(q, N, 26), dtype=np.uint64)
+    fa = oracle.forward(a, [q])
+    assert sorted(oracle.automorph_transformed(fa, [q], 5).tolist()) == sorted(fa.tolist())
