@@ -199,6 +199,24 @@ def run_gpu(args):
                            "hbm_frac_with_tables": round((coeff_bytes + table_bytes) / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         _log(f"[bench] whole transforms: {whole}")
         extra["c2_whole_transform"] = whole
+        # Automorphism sigma_5 of every limb (coefficient domain, then the forward
+        # transform's slot order) from the rotating sets into two output buffers:
+        # algorithmic bytes = every word read once and written once.
+        outs = [empty_device((P, L, N), 64) for _ in range(2)]
+        auto = {}
+        k_inv5 = pow(5, -1, 2 * N)
+        for name, k, tr in (("coefficient", 5, False), ("coefficient_k_inv5", k_inv5, False),
+                            ("transformed", 5, True)):
+            def call(k=k, tr=tr):
+                j = next(ctr)
+                plan.automorph(outs[j % 2], X[j % args.sets], k, tr, stream)
+            t = _time(torch, call, 4 * args.sets, stream)
+            auto[name] = {"us": round(t * 1e3, 2),
+                          "alg_GBps": round(coeff_bytes / (t * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(coeff_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del outs
+        _log(f"[bench] automorphism k=5: {auto}")
+        extra["c2_automorph_k5"] = auto
         extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
     return value, ms_per_step, roofline, extra
 

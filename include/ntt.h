@@ -143,6 +143,21 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const vo
 ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, uint32_t rows,
                    uint32_t cols, uint32_t num_operands, void* stream);
 
+/* Automorphism sigma_k of R_q = Z_q[x]/(x^N+1): b(x) = a(x^k) for odd k,
+ * 1 <= k < 2N, on every limb of in[batch][L][N] into out[batch][L][N] (Sec. III
+ * names Automorph among the CKKS operators around the NTT; Sec. IV-B builds
+ * repacking on it).  Coefficient domain by default: the term a_i x^i becomes
+ * a_i x^(i k mod 2N), negated when that exponent is N or more (x^N = -1).  With
+ * NTT_AUTOMORPH_TRANSFORMED, in and out are in the forward transform's output
+ * order and the map is a permutation of slots: slot j holds the value at
+ * psi^(2 brv(j) + 1), and out slot j takes the input slot whose exponent is
+ * (2 brv(j) + 1) k mod 2N.  Inputs canonical in [0, q); outputs likewise.
+ * Errors (NTT_EINVAL, before any launch): null pointers, even k or k >= 2N,
+ * unknown flags, out overlapping in, batch * L * N >= 2^32 words. */
+#define NTT_AUTOMORPH_TRANSFORMED 1u
+ntt_status ntt_automorph(ntt_plan_t plan, void* out, const void* in, uint32_t batch, uint32_t k,
+                         uint32_t flags, void* stream);
+
 /* External product of the TFHE CMux (Sec. II-B, Sec. IV-A: decomposed operands
  * are transformed, multiplied-and-accumulated against a key in the transform
  * domain, and the accumulators are inverse-transformed):

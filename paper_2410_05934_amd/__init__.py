@@ -16,7 +16,7 @@ import os
 import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
-           "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_ROW_RADIX4", "FLAG_FUSED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
+           "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_ROW_RADIX4", "FLAG_FUSED", "AUTOMORPH_TRANSFORMED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
            "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
            "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
            "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
@@ -31,6 +31,7 @@ FLAG_FORCE_INT64 = 1 << 16
 FLAG_ROW_RADIX8 = 1 << 17
 FLAG_FUSED = 1 << 18
 FLAG_ROW_RADIX4 = 1 << 19
+AUTOMORPH_TRANSFORMED = 1
 
 STATUS = {0: "NTT_OK", 1: "NTT_EINVAL", 2: "NTT_ENOTPRIME", 3: "NTT_ENOROOT", 4: "NTT_ERANGE",
           5: "NTT_ENOMEM", 6: "NTT_EDEVICE", 7: "NTT_EBUSY", 8: "NTT_ETIMEOUT"}
@@ -67,6 +68,7 @@ _SIGS = {
     "ntt_mac": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
+    "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
     "ntt_plan_split_for": [_vp, _u32, ctypes.POINTER(_u32)],
@@ -448,6 +450,18 @@ class Plan:
         _check(lib().ntt_external_product(self._h, out.data_ptr(), a.data_ptr(), key.data_ptr(),
                                           rows, cols, P, _stream_handle(stream)),
                "ntt_external_product")
+        return out
+
+    def automorph(self, out, a, k: int, transformed: bool = False, stream=None):
+        """out = sigma_k(a): a(x) -> a(x^k) per limb, k odd < 2N; coefficient domain,
+        or the forward transform's slot order with transformed=True (out must not
+        overlap a)."""
+        n = self._batch_of(a, "a")
+        if self._batch_of(out, "out") != n:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_automorph(self._h, out.data_ptr(), a.data_ptr(), n, int(k),
+                                   AUTOMORPH_TRANSFORMED if transformed else 0,
+                                   _stream_handle(stream)), "ntt_automorph")
         return out
 
     def polymul(self, out, a, b, stream=None):

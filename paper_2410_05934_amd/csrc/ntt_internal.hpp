@@ -55,6 +55,7 @@ inline uint32_t polymul_split(const ntt_plan_s* p, uint32_t n1) {
 
 ntt_status fail(ntt_status st, const char* fmt, ...);
 ntt_status hip_fail(hipError_t e, const char* what);
+void clear_error();  // empties the calling thread's last-error message
 
 // Per-launch timing (enabled through ntt_stats_enable).  When enabled, the
 // launch is bracketed by two events on its own stream.

@@ -38,7 +38,7 @@ ntt_status nttk::hip_fail(hipError_t e, const char* what) {
               hipGetErrorString(e));
 }
 
-static void clear_error() { g_last_error.clear(); }
+void nttk::clear_error() { g_last_error.clear(); }
 
 #include "numtheory.hpp"
 
