@@ -249,3 +249,43 @@ def automorph_transformed(ahat, moduli, k: int) -> np.ndarray:
     """sigma_k on transformed data (the forward transform's output order): the
     transform of sigma_k applied to the polynomial whose transform is ahat."""
     return forward(automorph(inverse(ahat, moduli), moduli, k), moduli)
+
+
+# -- gadget decomposition and the external product (Sec. II-B, Sec. IV-A) --------
+
+def decompose(ct, moduli, levels: int, log_base: int) -> np.ndarray:
+    """Signed base-B digits (B = 2^log_base) of every coefficient, the Decompose
+    step of the external product.  Digit j of a is taken from the remainder r_j
+    (r_0 = a): d_j = r_j mod B, moved to [-B/2, B/2) by subtracting B when it is
+    B/2 or more, and r_(j+1) = (r_j - d_j) / B; the top digit is the remainder
+    itself, d_(levels-1) = r_(levels-1).  Then a = sum_j d_j B^j exactly.
+
+    ct[num_ct][comps][L][N] (words in [0, q)) -> operands[num_ct][comps*levels][L][N];
+    operand c*levels + j holds d_j mod q_l of component c.
+    """
+    x = _u64(ct)
+    num_ct, comps, L, N = x.shape
+    mod = [int(q) for q in np.atleast_1d(moduli)]
+    B = 1 << log_base
+    out = np.empty((num_ct, comps * levels, L, N), dtype=np.uint64)
+    for l in range(L):
+        q = mod[l]
+        r = x[:, :, l, :].astype(np.int64)
+        for j in range(levels):
+            if j < levels - 1:
+                d = r % B
+                d = np.where(d >= B // 2, d - B, d)
+                r = (r - d) // B
+            else:
+                d = r
+            out[:, j::levels, l, :] = np.where(d < 0, d + q, d).astype(np.uint64)
+    return out
+
+
+def external_product_decomposed(ct, key, moduli, levels: int, log_base: int, cols: int) -> np.ndarray:
+    """out[g][c] = INTT( sum_r NTT(decompose(ct[g])[r]) (.) key[r][c] ): the external
+    product of each ciphertext g with a key of comps*levels rows (transform domain)."""
+    ops = decompose(ct, moduli, levels, log_base)
+    num_ct, rows, L, N = ops.shape
+    f = forward(ops.reshape(num_ct * rows, L, N), moduli)
+    return inverse(mac(f, key, moduli, rows, cols), moduli)

@@ -333,3 +333,92 @@ def test_automorph_transformed_permutes_slots(q):
     a = np.array(_rand(q, N, 26), dtype=np.uint64)
     fa = oracle.forward(a, [q])
     assert sorted(oracle.automorph_transformed(fa, [q], 5).tolist()) == sorted(fa.tolist())
+
+
+# -- gadget decomposition ---------------------------------------------------------
+
+def _digits_bruteforce(a, levels, log_base):
+    """The unique digit tuple with d_j in [-B/2, B/2) below the top and the top in
+    [-B/2, B/2] whose weighted sum is a, by exhaustive search (tiny B only)."""
+    B = 1 << log_base
+    import itertools
+    low = range(-B // 2, B // 2)
+    found = []
+    for ds in itertools.product(low, repeat=levels - 1):
+        rest = a - sum(d * B ** j for j, d in enumerate(ds))
+        if rest % B ** (levels - 1) == 0:
+            top = rest // B ** (levels - 1)
+            if -B // 2 <= top <= B // 2:
+                found.append(list(ds) + [top])
+    assert len(found) == 1, (a, found)
+    return found[0]
+
+
+def test_decompose_matches_exhaustive_search():
+    q = 97  # q = 1 mod 2N for N = 16; 7 bits, levels * log_base - 1 = 8 >= 7
+    for levels, log_base in [(3, 3), (2, 4), (4, 2)]:
+        if levels * log_base - 1 < 7:
+            continue
+        a = np.arange(q, dtype=np.uint64).reshape(1, 1, 1, q)
+        d = oracle.decompose(a, [q], levels, log_base)
+        for v in range(q):
+            want = _digits_bruteforce(v, levels, log_base)
+            got = [int(d[0, j, 0, v]) for j in range(levels)]
+            assert got == [w % q for w in want], (levels, log_base, v)
+
+
+@pytest.mark.parametrize("q,levels,log_base", [(4294957057, 3, 11), (4294957057, 4, 9),
+                                                (1125899903827969, 5, 11),
+                                                (4611686018425815041, 3, 21)])
+def test_decompose_reconstructs_exactly_with_bounded_digits(q, levels, log_base):
+    B = 1 << log_base
+    rng = random.Random(31)
+    vals = [0, 1, q - 1, q // 2, B // 2, B // 2 - 1, B - 1, B ** (levels - 1) * (B // 2)]
+    vals = [v for v in vals if v < q] + [rng.randrange(q) for _ in range(300)]
+    a = np.array(vals, dtype=np.uint64).reshape(1, 1, 1, -1)
+    d = oracle.decompose(a, [q], levels, log_base)
+    for i, v in enumerate(vals):
+        digs = [int(d[0, j, 0, i]) for j in range(levels)]
+        signed = [x - q if x > q // 2 else x for x in digs]
+        assert sum(s * B ** j for j, s in enumerate(signed)) == v
+        assert all(-B // 2 <= s < B // 2 for s in signed[:-1])
+        assert -B // 2 <= signed[-1] <= B // 2
+
+
+def test_decompose_layout_components_and_limbs():
+    """Operand c*levels + j of ciphertext g holds digit j of component c, per limb."""
+    mods = [4294957057, 4294828033]
+    ct = np.array([[[[5, 2 ** 31 + 7], [9, 3]], [[1, 2], [3, 4]]]], dtype=np.uint64)  # [1][2][2][2]
+    d = oracle.decompose(ct, mods, 3, 11)
+    assert d.shape == (1, 6, 2, 2)
+    for c in range(2):
+        for l in range(2):
+            for n in range(2):
+                v = int(ct[0, c, l, n])
+                digs = [int(d[0, c * 3 + j, l, n]) for j in range(3)]
+                signed = [x - mods[l] if x > mods[l] // 2 else x for x in digs]
+                assert sum(s * 2 ** (11 * j) for j, s in enumerate(signed)) == v
+
+
+def test_external_product_decomposed_is_the_gadget_product():
+    """sum_j d_j B^j = a, so with key rows key[c*levels + j][col] = B^j * s_c,col the
+    decomposed external product equals the plain product a_c * s_c,col summed over c
+    (checked against the big-integer schoolbook product)."""
+    q, N, levels, log_base, comps, cols = 4294957057, 16, 3, 11, 2, 2
+    rng = random.Random(32)
+    ct = np.array([[[rng.randrange(q) for _ in range(N)]] for _ in range(comps)],
+                  dtype=np.uint64).reshape(1, comps, 1, N)
+    s = [[[rng.randrange(q) for _ in range(N)] for _ in range(cols)] for _ in range(comps)]
+    key = np.empty((comps * levels, cols, 1, N), dtype=np.uint64)
+    for c in range(comps):
+        for j in range(levels):
+            for col in range(cols):
+                scaled = np.array([(v * pow(2, log_base * j, q)) % q for v in s[c][col]], dtype=np.uint64)
+                key[c * levels + j, col, 0] = oracle.forward(scaled, [q])
+    out = oracle.external_product_decomposed(ct, key, [q], levels, log_base, cols)
+    for col in range(cols):
+        want = [0] * N
+        for c in range(comps):
+            prod = py_ref.negacyclic_schoolbook([int(v) for v in ct[0, c, 0]], s[c][col], q)
+            want = [(w + p) % q for w, p in zip(want, prod)]
+        assert [int(v) for v in out[0, col, 0]] == want
