@@ -270,9 +270,20 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
     def c3_fused():
         p3.external_product(acc2, a, key, rows, cols, stream)
 
+    # The same product from the ciphertexts themselves: G RLWE ciphertexts of
+    # k+1 = 2 components, each coefficient split into 3 signed digits of base
+    # 2^11 inside the kernel (rows = 2 x 3 = 6 operands per ciphertext).
+    ct = to_device(synth.uniform_poly(8, [q], G * 2, N), 32).reshape(G, 2, 1, N)
+    key4 = key.reshape(rows, cols, 1, N)
+    acc3 = empty_device((G, cols, 1, N), 32)
+
+    def c3_decomposed():
+        p3.external_product_decomposed(acc3, ct, key4, 3, 11, stream)
+
     tb = _time(torch, c3_batched, 20, stream)
     tp = _time(torch, c3_plain, 3, stream)
     tf = _time(torch, c3_fused, 20, stream)
+    td = _time(torch, c3_decomposed, 20, stream)
     copy_ms = _time(torch, lambda: work.copy_(a), 20, stream)
     torch.cuda.synchronize()
     n3 = Pn + G * cols
@@ -282,7 +293,10 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
                       "batched_over_plain": round(tp / tb, 2),
                       "external_product_us": round(tf * 1e3, 2),
                       "external_product_ntt_per_s": n3 / (tf * 1e-3),
-                      "external_product_same_words": bool(torch.equal(acc, acc2))}
+                      "external_product_same_words": bool(torch.equal(acc, acc2)),
+                      "decomposed_ciphertexts": G,
+                      "external_product_decomposed_us": round(td * 1e3, 2),
+                      "external_product_decomposed_ntt_per_s": (G * rows + G * cols) / (td * 1e-3)}
     # C1 latency: one 2^10 forward + inverse, u32.
     q1 = synth.c1_prime(0)
     p1 = ntt.Plan(N, [q1], 32)

@@ -174,6 +174,30 @@ ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const
                                 uint32_t rows, uint32_t cols, uint32_t num_operands,
                                 void* stream);
 
+/* External product of RLWE ciphertexts with the gadget decomposition fused in
+ * (Sec. II-B: RGSW keys of (k+1) x (k+1) l RLWE rows; Sec. IV-A: Decompose, NTT
+ * and MAC of a batched CMux).  Each coefficient a of component c of ciphertext g
+ * is split into `levels` signed digits in base B = 2^log_base: from the
+ * remainder r (initially a), a lower digit is r mod B moved to [-B/2, B/2) and
+ * r becomes (r - d) / B; the top digit is the last remainder, so
+ * a = sum_j d_j B^j exactly.  Digit j of component c is operand row
+ * r = c * levels + j (as a residue mod q), and
+ *   out[g][col] = INTT( sum_r NTT(digit row r of ct[g]) (.) key[r][col] ).
+ *   ct    [num_ct][comps][L][N], natural order, not modified
+ *   key   [comps * levels][cols][L][N], transform domain
+ *   out   [num_ct][cols][L][N], natural order; must not alias ct or key
+ * Requires q <= 2^(levels * log_base - 1) for every limb (the top digit stays in
+ * [0, B/2]), levels * log_base <= 64 and 1 <= log_base <= 32; the operands, out
+ * and key must each hold
+ * fewer than 2^32 words (else NTT_EINVAL).  The same words as decomposing into
+ * a buffer and calling ntt_external_product on it.  For N <= 2^12 with
+ * cols <= comps * levels one launch per class decomposes while it loads;
+ * other shapes decompose into a stream-ordered workspace first. */
+ntt_status ntt_external_product_decomposed(ntt_plan_t plan, void* out, const void* ct,
+                                           const void* key, uint32_t num_ct, uint32_t comps,
+                                           uint32_t levels, uint32_t log_base, uint32_t cols,
+                                           void* stream);
+
 /* Negacyclic product c = a * b mod (x^N + 1) per limb, through Eq. (1):
  * out, a, b are [batch][L][N] in natural order; a and b are not modified;
  * out must not alias a or b.  A two-pass product (N above the single-pass

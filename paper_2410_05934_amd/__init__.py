@@ -69,6 +69,7 @@ _SIGS = {
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_external_product_decomposed": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
     "ntt_plan_split_for": [_vp, _u32, ctypes.POINTER(_u32)],
@@ -450,6 +451,25 @@ class Plan:
         _check(lib().ntt_external_product(self._h, out.data_ptr(), a.data_ptr(), key.data_ptr(),
                                           rows, cols, P, _stream_handle(stream)),
                "ntt_external_product")
+        return out
+
+    def external_product_decomposed(self, out, ct, key, levels: int, log_base: int, stream=None):
+        """out[g][col] = INTT(sum_r NTT(digit row r of ct[g]) (.) key[r][col]) with
+        ct [num_ct][comps][L][N], key [comps*levels][cols][L][N], out [num_ct][cols][L][N]."""
+        if ct.dim() != 4 or key.dim() != 4 or out.dim() != 4:
+            raise ValueError("ct, key and out are [count][rows][L][N]")
+        num_ct, comps = int(ct.shape[0]), int(ct.shape[1])
+        cols = int(key.shape[1])
+        if int(key.shape[0]) != comps * levels:
+            raise ValueError("key must have comps*levels rows")
+        if tuple(out.shape[:2]) != (num_ct, cols):
+            raise ValueError("out must be [num_ct][cols][L][N]")
+        for t, name in ((ct, "ct"), (key, "key"), (out, "out")):
+            self._batch_of(t, name)
+        _check(lib().ntt_external_product_decomposed(self._h, out.data_ptr(), ct.data_ptr(),
+                                                     key.data_ptr(), num_ct, comps, levels,
+                                                     log_base, cols, _stream_handle(stream)),
+               "ntt_external_product_decomposed")
         return out
 
     def automorph(self, out, a, k: int, transformed: bool = False, stream=None):

@@ -11,5 +11,6 @@ template hipError_t polymul_cls<ArI64>(const ntt_plan_s*, int, void*, const void
 template hipError_t mac_cls<ArI64>(const ntt_plan_s*, int, void*, const void*, const void*,
                                    uint32_t, uint32_t, uint32_t, hipStream_t);
 template hipError_t xprod_cls<ArI64>(const ntt_plan_s*, int, void*, const void*, const void*,
-                                    uint32_t, uint32_t, uint32_t, hipStream_t);
+                                    uint32_t, uint32_t, uint32_t, hipStream_t, uint32_t,
+                                    uint32_t, uint32_t);
 }  // namespace nttk

@@ -351,16 +351,26 @@ hipError_t launch_xprod_n(const XpArgs& x, uint32_t groups, hipStream_t s) {
   using S = RowShape<LOGN2, 4>;
   const uint32_t threads = x.rows * S::TPC;
   const size_t lds = (size_t)x.rows * ((1u << LOGN2) + (1u << LOGN2) / 16) * sizeof(typename A::V);
-  LaunchTimer t("xprod", A::kName, LOGN2, false, false,
+  LaunchTimer t(x.levels ? "xprod_dec" : "xprod", A::kName, LOGN2, false, false,
                 ((uint64_t)groups * x.cols * x.n_cls) << LOGN2, s);
-  hipLaunchKernelGGL((xprod_kernel<A, LOGN2>), dim3(groups * x.n_cls), dim3(threads), lds, s, x);
+  if (x.levels)
+    hipLaunchKernelGGL((xprod_kernel<A, LOGN2, true>), dim3(groups * x.n_cls), dim3(threads), lds, s, x);
+  else
+    hipLaunchKernelGGL((xprod_kernel<A, LOGN2>), dim3(groups * x.n_cls), dim3(threads), lds, s, x);
   return hipGetLastError();
 }
 
+// comps / levels / log_base: the operands are the digits of ciphertexts in `a`
+// (levels = 0: the operands themselves are in `a`).
 template <class A>
 hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
-                     uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s) {
+                     uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s,
+                     uint32_t comps = 0, uint32_t levels = 0, uint32_t log_base = 0) {
   XpArgs x;
+  x.comps = comps;
+  x.levels = levels;
+  x.log_base = log_base;
+  x.dec_offset = levels ? digit_offset(levels, log_base) : 0;
   x.dst = out;
   x.a = a;
   x.key = key;

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ntt.h"
+#include "decompose.hpp"
 #include "modarith.hpp"
 #include "ntt_internal.hpp"
 
@@ -170,7 +171,8 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
                    uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
 template <class A>
 hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
-                     uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
+                     uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s,
+                     uint32_t comps, uint32_t levels, uint32_t log_base);
 #define NTT_EXTERN_CLASS(A)                                                                   \
   extern template hipError_t transform_cls<A>(const ntt_plan_s*, int, void*, uint32_t, bool,  \
                                               uint32_t, uint32_t*, hipStream_t);              \
@@ -182,7 +184,8 @@ hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const
   extern template hipError_t mac_cls<A>(const ntt_plan_s*, int, void*, const void*,           \
                                         const void*, uint32_t, uint32_t, uint32_t, hipStream_t); \
   extern template hipError_t xprod_cls<A>(const ntt_plan_s*, int, void*, const void*,         \
-                                          const void*, uint32_t, uint32_t, uint32_t, hipStream_t);
+                                          const void*, uint32_t, uint32_t, uint32_t, hipStream_t, \
+                                          uint32_t, uint32_t, uint32_t);
 NTT_EXTERN_CLASS(ArF64S)
 NTT_EXTERN_CLASS(ArF64L)
 NTT_EXTERN_CLASS(ArI64)
@@ -200,6 +203,34 @@ NTT_EXTERN_CLASS(ArI64)
       if (e_ != hipSuccess) return hip_fail(e_, "kernel launch");                \
     }                                                                            \
   } while (0)
+
+// Digits of ciphertexts [num_ct][comps][L][N] into operands
+// [num_ct][comps * levels][L][N] (operand c * levels + j = digit j of component c).
+struct DecArgs {
+  void* out;
+  const void* ct;
+  const LimbDev* limbs;
+  uint32_t L, log_n, comps, levels, log_base;
+  uint32_t total;  // output words, < 2^32
+  uint64_t offset;  // digit_offset(levels, log_base)
+};
+
+template <class W>
+static __global__ void __launch_bounds__(256) decompose_kernel(DecArgs d) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= d.total) return;
+  const uint32_t n = e & ((1u << d.log_n) - 1u);
+  uint32_t rest = e >> d.log_n;
+  const uint32_t l = rest % d.L;
+  rest /= d.L;
+  const uint32_t rows = d.comps * d.levels;
+  const uint32_t r = rest % rows;
+  const uint32_t g = rest / rows;
+  const uint32_t comp = r / d.levels;
+  const uint32_t j = r - comp * d.levels;
+  const W x = static_cast<const W*>(d.ct)[((((uint64_t)g * d.comps + comp) * d.L + l) << d.log_n) + n];
+  static_cast<W*>(d.out)[e] = signed_digit<W>(x, j, d.levels, d.log_base, d.offset, d.limbs[l].q);
+}
 
 static __global__ void fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -422,7 +453,7 @@ ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const
     return fail(NTT_EINVAL, "out and key must each hold < 2^32 words");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (xprod_fits(plan, rows, cols, key)) {
-    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s)));
+    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s, 0u, 0u, 0u)));
     return NTT_OK;
   }
   // Other shapes: forward a copy of the operands, MAC, inverse.
@@ -435,6 +466,69 @@ ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const
   if (st == NTT_OK) st = ntt_forward(plan, ws, num_operands, stream);
   if (st == NTT_OK) st = ntt_mac(plan, out, ws, key, rows, cols, num_operands, stream);
   if (st == NTT_OK) st = ntt_inverse(plan, out, (uint32_t)(groups * cols), stream);
+  (void)hipFreeAsync(ws, s);
+  return st;
+}
+
+ntt_status ntt_external_product_decomposed(ntt_plan_t plan, void* out, const void* ct,
+                                           const void* key, uint32_t num_ct, uint32_t comps,
+                                           uint32_t levels, uint32_t log_base, uint32_t cols,
+                                           void* stream) {
+  clear_error();
+  if (!plan) return fail(NTT_EINVAL, "null plan");
+  if (!out || !ct || !key) return fail(NTT_EINVAL, "null data");
+  if (num_ct == 0 || comps == 0 || levels == 0 || cols == 0)
+    return fail(NTT_EINVAL, "num_ct, comps, levels and cols must be >= 1");
+  if (log_base == 0 || log_base > 32) return fail(NTT_EINVAL, "log_base=%u not in 1..32", log_base);
+  if (out == ct || out == key) return fail(NTT_EINVAL, "out must not alias ct or key");
+  const uint64_t span = (uint64_t)levels * log_base;  // digits cover 2^(span - 1)
+  if (span > 64) return fail(NTT_EINVAL, "levels * log_base = %llu exceeds 64",
+                             (unsigned long long)span);
+  for (uint32_t l = 0; l < plan->L; ++l) {
+    if (span < 64 && plan->moduli[l] > (1ull << (span - 1)))
+      return fail(NTT_EINVAL, "levels * log_base = %llu too small for q=%llu (need q <= 2^%llu)",
+                  (unsigned long long)span, (unsigned long long)plan->moduli[l],
+                  (unsigned long long)(span - 1));
+  }
+  const uint64_t rows = (uint64_t)comps * levels;
+  const uint64_t poly = (uint64_t)plan->L << plan->log_n;
+  const uint64_t num_operands = (uint64_t)num_ct * rows;
+  if (num_operands * poly >= (1ull << 32) || (uint64_t)num_ct * cols * poly >= (1ull << 32) ||
+      rows * cols * poly >= (1ull << 32))
+    return fail(NTT_EINVAL, "operands, out and key must each hold < 2^32 words");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (xprod_fits(plan, (uint32_t)rows, cols, key)) {
+    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, ct, key, (uint32_t)rows, cols,
+                                        (uint32_t)num_operands, s, comps, levels, log_base)));
+    return NTT_OK;
+  }
+  // Other shapes: the digits into a stream-ordered workspace, then the external
+  // product of those operands.
+  const size_t bytes = (size_t)(num_operands * poly) * (plan->word_bits / 8);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, bytes, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(decomposition workspace)");
+  DecArgs d;
+  d.out = ws;
+  d.ct = ct;
+  d.limbs = plan->d_limbs;
+  d.L = plan->L;
+  d.log_n = plan->log_n;
+  d.comps = comps;
+  d.levels = levels;
+  d.log_base = log_base;
+  d.total = (uint32_t)(num_operands * poly);
+  d.offset = digit_offset(levels, log_base);
+  const uint32_t blocks = (uint32_t)(((uint64_t)d.total + 255) / 256);
+  if (plan->word_bits == 32)
+    hipLaunchKernelGGL(decompose_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL(decompose_kernel<uint64_t>, dim3(blocks), dim3(256), 0, s, d);
+  e = hipGetLastError();
+  ntt_status st = NTT_OK;
+  if (e != hipSuccess) st = hip_fail(e, "kernel launch");
+  if (st == NTT_OK) st = ntt_external_product(plan, out, ws, key, (uint32_t)rows, cols,
+                                              (uint32_t)num_operands, stream);
   (void)hipFreeAsync(ws, s);
   return st;
 }

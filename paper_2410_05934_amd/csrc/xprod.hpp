@@ -13,6 +13,7 @@
 //   copy, ntt_mac and ntt_inverse, with one launch and no intermediate in HBM.
 #pragma once
 
+#include "decompose.hpp"
 #include "ntt_kernels.hpp"
 
 namespace nttk {
@@ -20,18 +21,23 @@ namespace nttk {
 struct XpArgs {
   void* dst;                  // [groups][cols][L][N], natural order
   const void* a;              // [num_operands][L][N], natural order, not modified
+                              // (decomposing: [groups][comps][L][N] ciphertexts)
   const void* key;            // [rows][cols][L][N], transform domain
   const LimbDev* limbs;
   const uint32_t* cls_limbs;  // limbs of this launch's class
   uint32_t n_cls;
   uint32_t L;
   uint32_t rows, cols, num_operands;
+  uint32_t comps, levels, log_base;  // decomposing: rows = comps * levels
+  uint64_t dec_offset;               // digit_offset(levels, log_base)
 };
 
 // Grid: groups * n_cls workgroups of rows * (N/16) threads; dynamic LDS of
 // rows regions of N + N/16 values (the padded chunk, also for N = 16 where the
 // row pass itself needs no LDS).  Requires cols <= rows.
-template <class A, int LOGN2>
+// DEC: the operands are not in memory; slot s = c * levels + j computes digit j
+// of component c of ciphertext `grp` as it loads (Decompose, fused).
+template <class A, int LOGN2, bool DEC = false>
 __global__ void __launch_bounds__(1024)
 xprod_kernel(XpArgs args) {
   constexpr int RB = 4;
@@ -76,11 +82,23 @@ xprod_kernel(XpArgs args) {
 
   // Forward transform of operand `slot` (a slot past the group's end
   // transforms the group's first operand and its result is never read).
-  const W* src = reinterpret_cast<const W*>(args.a) +
-                 (uint64_t)(first + (slot < nr ? slot : 0)) * poly_words + limb_off;
+  const uint32_t op = slot < nr ? slot : 0;
   V v[R];
+  if constexpr (DEC) {
+    const uint32_t comp = op / args.levels;
+    const uint32_t digit = op - comp * args.levels;
+    const W* src = reinterpret_cast<const W*>(args.a) +
+                   ((uint64_t)grp * args.comps + comp) * poly_words + limb_off;
 #pragma unroll
-  for (int u = 0; u < R; ++u) v[u] = ar.from_word(src[ins_bits<RB>(tt, u, H0)]);
+    for (int u = 0; u < R; ++u)
+      v[u] = ar.from_word(signed_digit<W>(src[ins_bits<RB>(tt, u, H0)], digit, args.levels,
+                                          args.log_base, args.dec_offset, ld.q));
+  } else {
+    const W* src = reinterpret_cast<const W*>(args.a) + (uint64_t)(first + op) * poly_words +
+                   limb_off;
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = ar.from_word(src[ins_bits<RB>(tt, u, H0)]);
+  }
   // One limb per workgroup: the tables are wave-uniform (scalar first-round twiddles).
   const typename A::TW* twf = uniform_ptr(reinterpret_cast<const typename A::TW*>(ld.twf));
   const typename A::TW* twi = uniform_ptr(reinterpret_cast<const typename A::TW*>(ld.twi));
