@@ -63,6 +63,7 @@ def _load():
                 "orc_mac": (None, [_u64p, ctypes.POINTER(_u64p), ctypes.POINTER(_u64p), u32, u64, u64]),
                 "orc_polymul": (i32, [_u64p, _u64p, _u64p, u32, u64]),
                 "orc_automorph": (None, [_u64p, _u64p, u32, u64, u64]),
+                "orc_bconv": (None, [_u64p, _u64p, u32, _u64p, u32, _u64p, u32]),
                 "orc_forward_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
                 "orc_inverse_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
                 "orc_num_cores": (i32, []),
@@ -289,3 +290,24 @@ def external_product_decomposed(ct, key, moduli, levels: int, log_base: int, col
     num_ct, rows, L, N = ops.shape
     f = forward(ops.reshape(num_ct * rows, L, N), moduli)
     return inverse(mac(f, key, moduli, rows, cols), moduli)
+
+
+# -- RNS basis conversion (Sec. III) -----------------------------------------------
+
+def bconv(x, src_moduli, dst_moduli) -> np.ndarray:
+    """Fast basis conversion of x[..., L, N] (residues mod src_moduli) to
+    y[..., M, N] (mod dst_moduli): y_j = sum_i [x_i (Q/q_i)^-1]_(q_i) (Q/q_i) mod p_j,
+    i.e. X + alpha Q mod p_j with 0 <= alpha < L."""
+    a = _u64(x)
+    src = _u64(np.atleast_1d(src_moduli))
+    dst = _u64(np.atleast_1d(dst_moduli))
+    L, M, N = src.shape[0], dst.shape[0], a.shape[-1]
+    rows = a.reshape(-1, L, N)
+    out = np.empty((rows.shape[0], M, N), dtype=np.uint64)
+    lib = _load()
+    for b in range(rows.shape[0]):
+        xb = np.ascontiguousarray(rows[b])
+        yb = np.empty((M, N), dtype=np.uint64)
+        lib.orc_bconv(_p(yb), _p(xb), N, _p(src), L, _p(dst), M)
+        out[b] = yb
+    return out.reshape(a.shape[:-2] + (M, N))

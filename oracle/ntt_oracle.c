@@ -275,6 +275,34 @@ void orc_automorph(uint64_t* b, const uint64_t* a, uint32_t N, uint64_t q, uint6
   }
 }
 
+/* RNS basis conversion (BConv; Sec. III lists it among the CKKS operators around
+ * the NTT).  x[L][N] holds residues of X modulo q_0..q_(L-1); the output
+ * y[M][N] holds, modulo each p_j,
+ *     sum_i [x_i * (Q/q_i)^-1 mod q_i] * (Q/q_i)        (Q = prod q_i),
+ * which is X + alpha*Q for an integer 0 <= alpha < L (the fast conversion: no
+ * correction of alpha).  Q/q_i is never formed: its residues are products of
+ * the other moduli, reduced as they are multiplied. */
+void orc_bconv(uint64_t* y, const uint64_t* x, uint32_t N, const uint64_t* q, uint32_t L,
+               const uint64_t* p, uint32_t M) {
+  for (uint32_t j = 0; j < M; ++j)
+    for (uint32_t n = 0; n < N; ++n) y[(size_t)j * N + n] = 0;
+  for (uint32_t i = 0; i < L; ++i) {
+    uint64_t qhat_mod_qi = 1;                 /* (Q/q_i) mod q_i */
+    for (uint32_t k = 0; k < L; ++k)
+      if (k != i) qhat_mod_qi = mulm(qhat_mod_qi, q[k] % q[i], q[i]);
+    const uint64_t qhat_inv = orc_invmod(qhat_mod_qi, q[i]);
+    for (uint32_t j = 0; j < M; ++j) {
+      uint64_t qhat_mod_pj = 1;               /* (Q/q_i) mod p_j */
+      for (uint32_t k = 0; k < L; ++k)
+        if (k != i) qhat_mod_pj = mulm(qhat_mod_pj, q[k] % p[j], p[j]);
+      for (uint32_t n = 0; n < N; ++n) {
+        const uint64_t t = mulm(x[(size_t)i * N + n], qhat_inv, q[i]);
+        y[(size_t)j * N + n] = addm(y[(size_t)j * N + n], mulm(t % p[j], qhat_mod_pj, p[j]), p[j]);
+      }
+    }
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Batched drivers: data[batch][L][N], moduli[L].  Independent (poly, limb)
  * rows are handed to a pool of threads; each row is transformed by the same

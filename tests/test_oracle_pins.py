@@ -422,3 +422,60 @@ def test_external_product_decomposed_is_the_gadget_product():
             prod = py_ref.negacyclic_schoolbook([int(v) for v in ct[0, c, 0]], s[c][col], q)
             want = [(w + p) % q for w, p in zip(want, prod)]
         assert [int(v) for v in out[0, col, 0]] == want
+
+
+# -- RNS basis conversion -----------------------------------------------------------
+
+def _crt(residues, moduli):
+    Q = 1
+    for m in moduli:
+        Q *= m
+    X = 0
+    for r, m in zip(residues, moduli):
+        Qi = Q // m
+        X += int(r) * Qi * pow(Qi, -1, m)
+    return X % Q, Q
+
+
+@pytest.mark.parametrize("L,M", [(1, 1), (3, 2), (5, 4), (12, 12)])
+def test_bconv_is_x_plus_alpha_q(L, M):
+    """Each output coefficient is (X + alpha Q) mod p_j with X the CRT value of the
+    inputs (big integers) and one integer 0 <= alpha < L shared by every p_j."""
+    from paper_2410_05934_amd import synth
+    pool = synth.primes_below(1 << 50, 1 << 17, L + M)
+    src, dst = pool[:L], pool[L:]
+    N = 32
+    x = synth.uniform_poly(70 + L, src, 2, N)
+    y = oracle.bconv(x, src, dst)
+    assert y.shape == (2, M, N)
+    for b in range(2):
+        for n in range(N):
+            X, Q = _crt([x[b, i, n] for i in range(L)], src)
+            alphas = set()
+            for j in range(M):
+                pj = dst[j]
+                # alpha with X + alpha*Q = y (mod p_j), alpha in [0, L)
+                cands = [al for al in range(L) if (X + al * Q - int(y[b, j, n])) % pj == 0]
+                assert len(cands) == 1, (b, n, j, cands)
+                alphas.add(cands[0])
+            assert len(alphas) == 1
+
+
+def test_bconv_small_values_are_exact_and_sum_is_explicit():
+    """The explicit sum in big integers, and: X = 0 maps to 0; one input modulus
+    (L = 1) is exact (alpha = 0): y_j = x_0 mod p_j."""
+    from paper_2410_05934_amd import synth
+    src = synth.primes_below(1 << 32, 1 << 17, 3)
+    dst = synth.primes_below(1 << 61, 1 << 17, 2)
+    N = 8
+    x = synth.uniform_poly(75, src, 1, N)
+    y = oracle.bconv(x, src, dst)
+    Q = src[0] * src[1] * src[2]
+    for n in range(N):
+        S = sum((int(x[0, i, n]) * pow(Q // src[i], -1, src[i]) % src[i]) * (Q // src[i])
+                for i in range(3))
+        assert [int(v) for v in y[0, :, n]] == [S % p for p in dst]
+    z = oracle.bconv(np.zeros((1, 3, N), dtype=np.uint64), src, dst)
+    assert not z.any()
+    one = oracle.bconv(x[:, :1], src[:1], dst)
+    assert [[int(v) for v in r] for r in one[0]] == [[int(v) % p for v in x[0, 0]] for p in dst]
