@@ -217,6 +217,21 @@ def run_gpu(args):
         del outs
         _log(f"[bench] automorphism k=5: {auto}")
         extra["c2_automorph_k5"] = auto
+        # Basis conversion of the 4 x 36-limb polynomials to 36 other 50-bit primes:
+        # 36 x (36 + 5) Shoup products per coefficient (five chunks of output moduli).
+        dst = synth.primes_below(1 << 50, 1 << 17, 2 * L)[L:]
+        conv = ntt.BasisConversion(N, moduli, dst, 64)
+        yb = empty_device((P, L, N), 64)
+
+        def bcall():
+            conv(yb, X[next(ctr) % args.sets], stream)
+        t = _time(torch, bcall, 2 * args.sets, stream)
+        prods = P * N * L * (L + (L + 7) // 8)
+        extra["c2_bconv_36_to_36"] = {"us": round(t * 1e3, 2),
+                                      "modmul_per_s": prods / (t * 1e-3),
+                                      "alg_GBps": round(2 * P * L * N * 8 / (t * 1e-3) / 1e9, 1)}
+        del yb, conv
+        _log(f"[bench] basis conversion 36 -> 36: {extra['c2_bconv_36_to_36']}")
         extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
     return value, ms_per_step, roofline, extra
 

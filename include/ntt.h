@@ -143,6 +143,27 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const vo
 ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, uint32_t rows,
                    uint32_t cols, uint32_t num_operands, void* stream);
 
+/* RNS basis conversion (BConv; Sec. III lists it among the CKKS operators
+ * around the NTT).  in[batch][L][N] holds residues of X modulo the source
+ * moduli q_0..q_(L-1) (coefficient domain); out[batch][M][N] receives, modulo
+ * each target modulus p_j,
+ *     sum_i [x_i (Q/q_i)^-1 mod q_i] (Q/q_i mod p_j)      (Q = prod q_i),
+ * that is X + alpha Q mod p_j for one integer 0 <= alpha < L per coefficient
+ * (the fast conversion; alpha is not corrected).
+ *   create: N a power of two in [2, 65536]; 1 <= L <= 64 distinct prime source
+ *           moduli and 1 <= M <= 4096 target moduli >= 2, all below 2^32
+ *           (word_bits 32) or 2^62 (word_bits 64); the constants go to the
+ *           current device.  Errors: NTT_EINVAL, NTT_ENOTPRIME, NTT_ERANGE,
+ *           NTT_ENOMEM / NTT_EDEVICE.
+ *   run:    in canonical residues; out must not overlap in; batch * L * N and
+ *           batch * M * N below 2^32 words (else NTT_EINVAL).  Asynchronous on
+ *           `stream`. */
+typedef struct ntt_bconv_s* ntt_bconv_t;
+ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
+                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits);
+ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, void* stream);
+ntt_status ntt_bconv_destroy(ntt_bconv_t h);
+
 /* Automorphism sigma_k of R_q = Z_q[x]/(x^N+1): b(x) = a(x^k) for odd k,
  * 1 <= k < 2N, on every limb of in[batch][L][N] into out[batch][L][N] (Sec. III
  * names Automorph among the CKKS operators around the NTT; Sec. IV-B builds

@@ -17,7 +17,7 @@ import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
            "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_ROW_RADIX4", "FLAG_FUSED", "AUTOMORPH_TRANSFORMED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
-           "RaggedBatch", "batch_ragged", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
+           "RaggedBatch", "batch_ragged", "BasisConversion", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
            "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
            "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
            "SERVER_SERIAL", "SERVER_DRY_RUN"]
@@ -69,6 +69,10 @@ _SIGS = {
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_bconv_create": [ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u64), _u32, ctypes.POINTER(_u64),
+                         _u32, _u32],
+    "ntt_bconv": [_vp, _vp, _vp, _u32, _vp],
+    "ntt_bconv_destroy": [_vp],
     "ntt_external_product_decomposed": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
@@ -139,6 +143,49 @@ class RaggedBatch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ntt_ragged_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BasisConversion:
+    """RNS basis conversion from src_moduli (L) to dst_moduli (M) for length N:
+    out[b][j] = sum_i [x_i (Q/q_i)^-1]_(q_i) (Q/q_i) mod p_j (X + alpha Q, 0 <= alpha < L)."""
+
+    def __init__(self, N: int, src_moduli, dst_moduli, word_bits: int = 64):
+        self.N, self.word_bits = int(N), int(word_bits)
+        self.L, self.M = len(src_moduli), len(dst_moduli)
+        src = (_u64 * self.L)(*[int(q) for q in src_moduli])
+        dst = (_u64 * self.M)(*[int(p) for p in dst_moduli])
+        self._h = _vp()
+        _check(lib().ntt_bconv_create(ctypes.byref(self._h), self.N, src, self.L, dst, self.M,
+                                      self.word_bits), "ntt_bconv_create")
+
+    def _batch(self, t, rows: int, name: str) -> int:
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+        if t.element_size() * 8 != self.word_bits:
+            raise ValueError(f"{name} element size does not match word_bits")
+        per = rows * self.N
+        if t.numel() == 0 or t.numel() % per:
+            raise ValueError(f"{name} has {t.numel()} elements, not a multiple of {per}")
+        return t.numel() // per
+
+    def __call__(self, out, x, stream=None):
+        b = self._batch(x, self.L, "x")
+        if self._batch(out, self.M, "out") != b:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_bconv(self._h, out.data_ptr(), x.data_ptr(), b, _stream_handle(stream)),
+               "ntt_bconv")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ntt_bconv_destroy(self._h)
             self._h = _vp()
 
     def __del__(self):

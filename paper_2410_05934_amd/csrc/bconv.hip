@@ -1,0 +1,326 @@
+// bconv.hip -- RNS basis conversion (BConv; Sec. III lists it among the CKKS
+// operators around the NTT, the other half of key switching's ModUp/ModDown).
+//
+// x[batch][L][N] holds residues of X modulo q_0..q_(L-1); the output
+// y[batch][M][N] holds, modulo each p_j,
+//     sum_i [x_i (Q/q_i)^-1 mod q_i] * (Q/q_i mod p_j)         (Q = prod q_i)
+// which is X + alpha Q for one integer 0 <= alpha < L (fast conversion, alpha
+// not corrected).
+//
+// One thread per (polynomial, coefficient).  Output moduli go in chunks of
+// kBconvChunk: for each chunk the thread walks the L source residues of its
+// coefficient (lanes with consecutive coefficients read consecutive words),
+// forms t_i = x_i w_i mod q_i and adds t_i (Q/q_i mod p_j) into the chunk's
+// accumulators, then stores one coalesced word per output modulus.  Every
+// constant is the same for all lanes (scalar loads) and every product has a
+// constant operand, so all products are Shoup products with precomputed
+// companions.  Re-forming t_i per chunk costs L products per chunk on top of
+// the L M of the sum (+1/8) and keeps the registers to the chunk's accumulators
+// whatever L and M are.  The work is VALU-bound for dozens of limbs, not
+// HBM-bound.
+//
+// When every modulus is below 2^50 - 2^10 the products run on the fp64 FMA
+// units instead (the exact product of the fp64 arithmetic classes: high part,
+// FMA error term, rounded quotient): a handful of full-rate fp64 operations
+// against some ten quarter-rate 32-bit multiplies for a 64-bit Shoup product.
+// Each term lies in (-7/8 p, 7/8 p), so eight of them are summed exactly in a
+// double before the sum is centred again.
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <vector>
+
+#include "ntt_internal.hpp"
+#include "numtheory.hpp"
+
+struct ntt_bconv_s {
+  int device = 0;
+  uint32_t N = 0, log_n = 0, L = 0, M = 0, word_bits = 0;
+  uint64_t* d_c1 = nullptr;  // [L][3]: q_i, w_i = (Q/q_i)^-1 mod q_i, floor(w_i 2^64 / q_i)
+  uint64_t* d_c2 = nullptr;  // [L][M][2]: (Q/q_i) mod p_j and its Shoup companion
+  uint64_t* d_p = nullptr;   // [M]
+  bool f64 = false;          // every modulus < 2^50 - 2^10: fp64 products
+  double* d_f1 = nullptr;    // [L][4]: q_i, 1/q_i, w_i, w_i/q_i
+  double* d_f2 = nullptr;    // [L][M][2]: (Q/q_i) mod p_j, that over p_j
+  double* d_fp = nullptr;    // [M][2]: p_j, 1/p_j
+};
+
+namespace nttk {
+
+struct BconvArgs {
+  void* out;
+  const void* in;
+  const uint64_t* c1;
+  const uint64_t* c2;
+  const uint64_t* p;
+  const double* f1;
+  const double* f2;
+  const double* fp;
+  uint32_t L, M, log_n;
+  uint32_t total;  // batch * N threads
+};
+
+constexpr uint32_t kBconvBlock = 256;
+
+// y w mod q up to one q: y w - floor(y ws / 2^64) q lies in [0, 2q) for any
+// 64-bit y when w < q < 2^63 and ws = floor(w 2^64 / q).
+__device__ __forceinline__ uint64_t shoup2(uint64_t y, uint64_t w, uint64_t ws, uint64_t q) {
+  return y * w - __umul64hi(y, ws) * q;
+}
+
+constexpr int kBconvChunk = 8;
+
+template <class W>
+__global__ void __launch_bounds__(kBconvBlock) bconv_kernel(BconvArgs a) {
+  constexpr int JB = kBconvChunk;
+  const uint32_t gid = blockIdx.x * kBconvBlock + threadIdx.x;
+  if (gid >= a.total) return;
+  const uint32_t n = gid & ((1u << a.log_n) - 1u);
+  const uint32_t b = gid >> a.log_n;
+  const W* x = static_cast<const W*>(a.in) + (((uint64_t)b * a.L) << a.log_n) + n;
+  W* y = static_cast<W*>(a.out) + (((uint64_t)b * a.M) << a.log_n) + n;
+  for (uint32_t j0 = 0; j0 < a.M; j0 += JB) {
+    const uint32_t jn = a.M - j0 < (uint32_t)JB ? a.M - j0 : (uint32_t)JB;
+    uint64_t acc[JB];  // each < 2p_j (p < 2^62: acc + product < 4p < 2^64)
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) acc[jj] = 0;
+    for (uint32_t i = 0; i < a.L; ++i) {
+      const uint64_t q = a.c1[3 * i], w = a.c1[3 * i + 1], ws = a.c1[3 * i + 2];
+      uint64_t t = shoup2((uint64_t)x[(uint64_t)i << a.log_n], w, ws, q);
+      t = t >= q ? t - q : t;
+      const uint64_t* ci = a.c2 + 2 * ((uint64_t)i * a.M + j0);
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        if ((uint32_t)jj < jn) {
+          const uint64_t p2 = 2 * a.p[j0 + jj];
+          acc[jj] += shoup2(t, ci[2 * jj], ci[2 * jj + 1], p2 >> 1);
+          acc[jj] = acc[jj] >= p2 ? acc[jj] - p2 : acc[jj];
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+      if ((uint32_t)jj < jn) {
+        const uint64_t p = a.p[j0 + jj];
+        y[(uint64_t)(j0 + jj) << a.log_n] = (W)(acc[jj] >= p ? acc[jj] - p : acc[jj]);
+      }
+    }
+  }
+}
+
+// x w mod q for x, w < q < 2^50 - 2^10 given wq = w/q: the exact value of
+// x w - c q with c the rounded quotient, in (-7/8 q, 7/8 q).
+__device__ __forceinline__ double f64_mulmod_pre(double x, double w, double wq, double q) {
+  const double h = x * w;
+  const double l = __builtin_fma(x, w, -h);
+  const double c = __builtin_rint(x * wq);
+  return __builtin_fma(-c, q, h) + l;
+}
+
+template <class W>
+__global__ void __launch_bounds__(kBconvBlock) bconv_f64_kernel(BconvArgs a) {
+  constexpr int JB = kBconvChunk;
+  const uint32_t gid = blockIdx.x * kBconvBlock + threadIdx.x;
+  if (gid >= a.total) return;
+  const uint32_t n = gid & ((1u << a.log_n) - 1u);
+  const uint32_t b = gid >> a.log_n;
+  const W* x = static_cast<const W*>(a.in) + (((uint64_t)b * a.L) << a.log_n) + n;
+  W* y = static_cast<W*>(a.out) + (((uint64_t)b * a.M) << a.log_n) + n;
+  for (uint32_t j0 = 0; j0 < a.M; j0 += JB) {
+    const uint32_t jn = a.M - j0 < (uint32_t)JB ? a.M - j0 : (uint32_t)JB;
+    double acc[JB];  // |acc| < p/2 + 2 after each centring, < 2^53 between
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) acc[jj] = 0.0;
+    for (uint32_t i = 0; i < a.L; ++i) {
+      const double* f = a.f1 + 4 * i;
+      double t = f64_mulmod_pre((double)x[(uint64_t)i << a.log_n], f[2], f[3], f[0]);
+      t = t < 0.0 ? t + f[0] : t;  // [x_i w_i]_(q_i) in [0, q_i)
+      const double* fi = a.f2 + 2 * ((uint64_t)i * a.M + j0);
+      const bool recentre = (i & 7u) == 7u;
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        if ((uint32_t)jj < jn) {
+          const double p = a.fp[2 * (j0 + jj)];
+          acc[jj] += f64_mulmod_pre(t, fi[2 * jj], fi[2 * jj + 1], p);
+          if (recentre)
+            acc[jj] = __builtin_fma(-__builtin_rint(acc[jj] * a.fp[2 * (j0 + jj) + 1]), p, acc[jj]);
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+      if ((uint32_t)jj < jn) {
+        const double p = a.fp[2 * (j0 + jj)], pinv = a.fp[2 * (j0 + jj) + 1];
+        double r = __builtin_fma(-__builtin_rint(acc[jj] * pinv), p, acc[jj]);
+        r = r < 0.0 ? r + p : r;
+        r = r >= p ? r - p : r;
+        y[(uint64_t)(j0 + jj) << a.log_n] = (W)(uint64_t)r;
+      }
+    }
+  }
+}
+
+template <class W>
+static hipError_t launch_bconv(const BconvArgs& a, bool f64, hipStream_t s) {
+  const uint32_t blocks = (uint32_t)(((uint64_t)a.total + kBconvBlock - 1) / kBconvBlock);
+  LaunchTimer t(f64 ? "bconv_f64" : "bconv", sizeof(W) == 4 ? "u32" : "u64", (int)a.log_n, false,
+                false, (uint64_t)a.total * a.M, s);
+  if (f64)
+    hipLaunchKernelGGL((bconv_f64_kernel<W>), dim3(blocks), dim3(kBconvBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((bconv_kernel<W>), dim3(blocks), dim3(kBconvBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+static void free_bconv(ntt_bconv_s* h) {
+  if (!h) return;
+  if (h->d_c1) (void)hipFree(h->d_c1);
+  if (h->d_c2) (void)hipFree(h->d_c2);
+  if (h->d_p) (void)hipFree(h->d_p);
+  if (h->d_f1) (void)hipFree(h->d_f1);
+  if (h->d_f2) (void)hipFree(h->d_f2);
+  if (h->d_fp) (void)hipFree(h->d_fp);
+  delete h;
+}
+
+}  // namespace nttk
+
+using namespace nttk;
+
+extern "C" {
+
+ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
+                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits) {
+  clear_error();
+  if (!out || !src_moduli || !dst_moduli) return fail(NTT_EINVAL, "null argument");
+  *out = nullptr;
+  if (N < 2 || N > (1u << 16) || (N & (N - 1)))
+    return fail(NTT_EINVAL, "N=%u is not a power of two in [2, 65536]", N);
+  if (L == 0 || L > 64) return fail(NTT_EINVAL, "L=%u source moduli (1 .. 64)", L);
+  if (M == 0 || M > 4096) return fail(NTT_EINVAL, "M=%u target moduli (1 .. 4096)", M);
+  if (word_bits != 32 && word_bits != 64) return fail(NTT_EINVAL, "word_bits=%u", word_bits);
+  const uint64_t bound = word_bits == 32 ? (1ull << 32) : (1ull << 62);
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint64_t q = src_moduli[i];
+    if (q >= bound) return fail(NTT_ERANGE, "source q=%llu too wide", (unsigned long long)q);
+    if (!nt_is_prime(q)) return fail(NTT_ENOTPRIME, "source q=%llu is not prime", (unsigned long long)q);
+    for (uint32_t k = 0; k < i; ++k)
+      if (src_moduli[k] == q) return fail(NTT_EINVAL, "source moduli must be distinct");
+  }
+  for (uint32_t j = 0; j < M; ++j) {
+    const uint64_t p = dst_moduli[j];
+    if (p < 2 || p >= bound) return fail(NTT_ERANGE, "target p=%llu out of range", (unsigned long long)p);
+  }
+  std::vector<uint64_t> c1(3 * (size_t)L), c2(2 * (size_t)L * M);
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint64_t q = src_moduli[i];
+    uint64_t qhat = 1;  // (Q/q_i) mod q_i
+    for (uint32_t k = 0; k < L; ++k)
+      if (k != i) qhat = nt_mul(qhat, src_moduli[k] % q, q);
+    const uint64_t w = nt_pow(qhat, q - 2, q);  // q prime
+    c1[3 * i] = q;
+    c1[3 * i + 1] = w;
+    c1[3 * i + 2] = (uint64_t)(((u128)w << 64) / q);
+    for (uint32_t j = 0; j < M; ++j) {
+      const uint64_t p = dst_moduli[j];
+      uint64_t m = 1 % p;  // (Q/q_i) mod p_j
+      for (uint32_t k = 0; k < L; ++k)
+        if (k != i) m = nt_mul(m, src_moduli[k] % p, p);
+      c2[2 * ((size_t)i * M + j)] = m;
+      c2[2 * ((size_t)i * M + j) + 1] = (uint64_t)(((u128)m << 64) / p);
+    }
+  }
+  ntt_bconv_s* h = new (std::nothrow) ntt_bconv_s();
+  if (!h) return fail(NTT_ENOMEM, "host allocation");
+  hipError_t e = hipGetDevice(&h->device);
+  h->N = N;
+  h->log_n = 0;
+  while ((1u << h->log_n) < N) ++h->log_n;
+  h->L = L;
+  h->M = M;
+  h->word_bits = word_bits;
+  if (e == hipSuccess) e = hipMalloc(&h->d_c1, c1.size() * 8);
+  if (e == hipSuccess) e = hipMalloc(&h->d_c2, c2.size() * 8);
+  if (e == hipSuccess) e = hipMalloc(&h->d_p, (size_t)M * 8);
+  if (e == hipSuccess) e = hipMemcpy(h->d_c1, c1.data(), c1.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_c2, c2.data(), c2.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_p, dst_moduli, (size_t)M * 8, hipMemcpyHostToDevice);
+  // fp64 products when every modulus fits the exact fp64 arithmetic
+  constexpr uint64_t kF64Bound = (1ull << 50) - (1ull << 10);
+  h->f64 = true;
+  for (uint32_t i = 0; i < L; ++i) h->f64 = h->f64 && src_moduli[i] < kF64Bound;
+  for (uint32_t j = 0; j < M; ++j) h->f64 = h->f64 && dst_moduli[j] < kF64Bound;
+  if (h->f64 && e == hipSuccess) {
+    std::vector<double> f1(4 * (size_t)L), f2(2 * (size_t)L * M), fp(2 * (size_t)M);
+    for (uint32_t i = 0; i < L; ++i) {
+      const double q = (double)c1[3 * i], w = (double)c1[3 * i + 1];
+      f1[4 * i] = q;
+      f1[4 * i + 1] = 1.0 / q;
+      f1[4 * i + 2] = w;
+      f1[4 * i + 3] = w * (1.0 / q);
+      for (uint32_t j = 0; j < M; ++j) {
+        const double m = (double)c2[2 * ((size_t)i * M + j)];
+        f2[2 * ((size_t)i * M + j)] = m;
+        f2[2 * ((size_t)i * M + j) + 1] = m * (1.0 / (double)dst_moduli[j]);
+      }
+    }
+    for (uint32_t j = 0; j < M; ++j) {
+      fp[2 * j] = (double)dst_moduli[j];
+      fp[2 * j + 1] = 1.0 / (double)dst_moduli[j];
+    }
+    e = hipMalloc(&h->d_f1, f1.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&h->d_f2, f2.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&h->d_fp, fp.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(h->d_f1, f1.data(), f1.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_f2, f2.data(), f2.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_fp, fp.data(), fp.size() * 8, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    free_bconv(h);
+    return hip_fail(e, "basis conversion constants");
+  }
+  *out = h;
+  return NTT_OK;
+}
+
+ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, void* stream) {
+  clear_error();
+  if (!h) return fail(NTT_EINVAL, "null basis conversion");
+  if (!out || !in) return fail(NTT_EINVAL, "null data");
+  if (batch == 0) return fail(NTT_EINVAL, "batch must be >= 1");
+  const uint64_t in_words = ((uint64_t)batch * h->L) << h->log_n;
+  const uint64_t out_words = ((uint64_t)batch * h->M) << h->log_n;
+  if (in_words >= (1ull << 32) || out_words >= (1ull << 32))
+    return fail(NTT_EINVAL, "batch * L * N and batch * M * N must be < 2^32 words");
+  const uint64_t wb = h->word_bits / 8;
+  const uintptr_t o = reinterpret_cast<uintptr_t>(out), i = reinterpret_cast<uintptr_t>(in);
+  if (o < i + in_words * wb && i < o + out_words * wb)
+    return fail(NTT_EINVAL, "out must not overlap in");
+  BconvArgs a;
+  a.out = out;
+  a.in = in;
+  a.c1 = h->d_c1;
+  a.c2 = h->d_c2;
+  a.p = h->d_p;
+  a.f1 = h->d_f1;
+  a.f2 = h->d_f2;
+  a.fp = h->d_fp;
+  a.L = h->L;
+  a.M = h->M;
+  a.log_n = h->log_n;
+  a.total = (uint32_t)((uint64_t)batch << h->log_n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = h->word_bits == 32 ? launch_bconv<uint32_t>(a, h->f64, s)
+                                          : launch_bconv<uint64_t>(a, h->f64, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return NTT_OK;
+}
+
+ntt_status ntt_bconv_destroy(ntt_bconv_t h) {
+  clear_error();
+  if (!h) return fail(NTT_EINVAL, "null basis conversion");
+  free_bconv(h);
+  return NTT_OK;
+}
+
+}  // extern "C"
