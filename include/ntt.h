@@ -159,8 +159,16 @@ ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, u
  *           batch * M * N below 2^32 words (else NTT_EINVAL).  Asynchronous on
  *           `stream`. */
 typedef struct ntt_bconv_s* ntt_bconv_t;
+/* When every modulus is below 2^50 - 2^10, N >= 32 and L, M >= 16 the sum runs
+ * on the int8 matrix cores (balanced base-256 digits, exact int32 sums; below
+ * 16 moduli on either side the vector units are faster).  NTT_BCONV_NO_MFMA
+ * keeps it on the vector units, NTT_BCONV_MFMA takes the matrix cores at any
+ * L and M (the fp64 bound and N >= 32 still apply); the words are the same. */
+#define NTT_BCONV_NO_MFMA 1u
+#define NTT_BCONV_MFMA 2u
 ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
-                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits);
+                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits,
+                            uint32_t flags);
 ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, void* stream);
 ntt_status ntt_bconv_destroy(ntt_bconv_t h);
 

@@ -32,6 +32,8 @@ FLAG_ROW_RADIX8 = 1 << 17
 FLAG_FUSED = 1 << 18
 FLAG_ROW_RADIX4 = 1 << 19
 AUTOMORPH_TRANSFORMED = 1
+BCONV_NO_MFMA = 1
+BCONV_MFMA = 2
 
 STATUS = {0: "NTT_OK", 1: "NTT_EINVAL", 2: "NTT_ENOTPRIME", 3: "NTT_ENOROOT", 4: "NTT_ERANGE",
           5: "NTT_ENOMEM", 6: "NTT_EDEVICE", 7: "NTT_EBUSY", 8: "NTT_ETIMEOUT"}
@@ -70,7 +72,7 @@ _SIGS = {
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_bconv_create": [ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u64), _u32, ctypes.POINTER(_u64),
-                         _u32, _u32],
+                         _u32, _u32, _u32],
     "ntt_bconv": [_vp, _vp, _vp, _u32, _vp],
     "ntt_bconv_destroy": [_vp],
     "ntt_external_product_decomposed": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _u32, _vp],
@@ -156,14 +158,18 @@ class BasisConversion:
     """RNS basis conversion from src_moduli (L) to dst_moduli (M) for length N:
     out[b][j] = sum_i [x_i (Q/q_i)^-1]_(q_i) (Q/q_i) mod p_j (X + alpha Q, 0 <= alpha < L)."""
 
-    def __init__(self, N: int, src_moduli, dst_moduli, word_bits: int = 64):
+    def __init__(self, N: int, src_moduli, dst_moduli, word_bits: int = 64, mfma=None):
+        """mfma: None lets the library choose, True asks for the int8 matrix cores
+        wherever they apply, False keeps the vector units."""
         self.N, self.word_bits = int(N), int(word_bits)
         self.L, self.M = len(src_moduli), len(dst_moduli)
         src = (_u64 * self.L)(*[int(q) for q in src_moduli])
         dst = (_u64 * self.M)(*[int(p) for p in dst_moduli])
         self._h = _vp()
         _check(lib().ntt_bconv_create(ctypes.byref(self._h), self.N, src, self.L, dst, self.M,
-                                      self.word_bits), "ntt_bconv_create")
+                                      self.word_bits,
+                                      0 if mfma is None else (BCONV_MFMA if mfma else BCONV_NO_MFMA)),
+               "ntt_bconv_create")
 
     def _batch(self, t, rows: int, name: str) -> int:
         if not t.is_cuda or not t.is_contiguous():

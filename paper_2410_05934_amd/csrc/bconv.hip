@@ -25,6 +25,24 @@
 // against some ten quarter-rate 32-bit multiplies for a 64-bit Shoup product.
 // Each term lies in (-7/8 p, 7/8 p), so eight of them are summed exactly in a
 // double before the sum is centred again.
+//
+// In that case the sum itself, a dense L x M contraction per coefficient, goes
+// to the int8 matrix cores.  Every t_i < 2^50 is written in balanced base-256
+// digits d_0..d_6 (d_a in [-128, 128) below the top, t = sum_a d_a 256^a), and
+// so is every constant m'_(i,a),j = (Q/q_i mod p_j) 256^a mod p_j (digits
+// e_0..e_6).  Then for each output modulus
+//     sum_i t_i (Q/q_i mod p_j) = sum_c 256^c D_c (mod p_j),
+//     D_c = sum_(i,a) d_a(t_i) e_c(m'_(i,a),j),
+// and the D_c are products of int8 matrices with exact int32 sums
+// (|D_c| <= 512 * 128 * 128 = 2^23).  The digits of t_i are one byte each of
+// z_i = (t_i + 128 (1 + 256 + ... + 256^5)) XOR 0x808080808080: eight bytes per
+// limb, the eighth zero, so one 64-bit word is one MFMA operand.  With
+// coefficients as the MFMA's columns and (output, digit c) as its rows, a lane
+// ends up with four D_c of four outputs for its own coefficient; four fp64
+// products with 256^c mod p_j, one exchange with the lane 32 away, and a
+// coalesced store finish the conversion.  The matrix work is 64 L M int8 MACs
+// per coefficient (about 10 us for 36 -> 36 limbs on 2^18 coefficients at the
+// dense int8 rate); the rest is the L x N reads and M x N writes.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -43,6 +61,9 @@ struct ntt_bconv_s {
   double* d_f1 = nullptr;    // [L][4]: q_i, 1/q_i, w_i, w_i/q_i
   double* d_f2 = nullptr;    // [L][M][2]: (Q/q_i) mod p_j, that over p_j
   double* d_fp = nullptr;    // [M][2]: p_j, 1/p_j
+  bool mfma = false;         // fp64-eligible, N >= 32, not switched off: int8 MFMA form
+  uint64_t* d_kop = nullptr; // MFMA constant operands [ceil(M/4)][ceil(L/2)][64 lanes]
+  double* d_om = nullptr;    // [M][8][2]: 256^c mod p_j and that over p_j
 };
 
 namespace nttk {
@@ -56,6 +77,8 @@ struct BconvArgs {
   const double* f1;
   const double* f2;
   const double* fp;
+  const uint64_t* kop;
+  const double* om;
   uint32_t L, M, log_n;
   uint32_t total;  // batch * N threads
 };
@@ -160,8 +183,97 @@ __global__ void __launch_bounds__(kBconvBlock) bconv_f64_kernel(BconvArgs a) {
   }
 }
 
+typedef int bconv_v16i __attribute__((ext_vector_type(16)));
+constexpr uint64_t kDigitOffset = 0x808080808080ull;  // 128 at digits 0..5
+
+// One wave per 32 coefficients of one polynomial (N >= 32); four waves per block.
+// SMAX bounds the k-steps (two limbs each) so that the digit words and two sets
+// of constant operands stay in registers: the operands of row tile rt + 1 are
+// requested before the products of row tile rt, hiding their L2 latency.
+template <class W, int SMAX>
+__global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t h = lane >> 5;    // which limb of a k-step / which digit half
+  const uint32_t col = lane & 31u; // the lane's coefficient within the tile
+  const uint32_t tile = (blockIdx.x * 4u + (threadIdx.x >> 6));
+  const uint64_t g = (uint64_t)tile * 32u + col;
+  if (tile * 32u >= a.total) return;  // whole waves leave together
+  const uint32_t n = (uint32_t)(g & ((1u << a.log_n) - 1u));
+  const uint64_t b = g >> a.log_n;
+  const uint32_t steps = (a.L + 1u) >> 1;
+  const W* x = static_cast<const W*>(a.in) + ((b * a.L) << a.log_n) + n;
+  // Digits of t_i = [x_i w_i]_(q_i) for the limbs i = 2s + h of this lane.
+  uint64_t z[SMAX];
+#pragma unroll
+  for (int st = 0; st < SMAX; ++st) {
+    z[st] = 0;
+    const uint32_t i = 2u * st + h;
+    if ((uint32_t)st < steps && i < a.L) {
+      const double* f = a.f1 + 4 * i;
+      double t = f64_mulmod_pre((double)x[(uint64_t)i << a.log_n], f[2], f[3], f[0]);
+      t = t < 0.0 ? t + f[0] : t;
+      z[st] = ((uint64_t)t + kDigitOffset) ^ kDigitOffset;
+    }
+  }
+  W* y = static_cast<W*>(a.out) + ((b * a.M) << a.log_n) + n;
+  const uint32_t row_tiles = (a.M + 3u) >> 2;
+  const uint64_t* kop = a.kop + lane;
+  uint64_t kcur[SMAX], knext[SMAX];
+#pragma unroll
+  for (int st = 0; st < SMAX; ++st) kcur[st] = (uint32_t)st < steps ? kop[(uint64_t)st * 64u] : 0;
+  for (uint32_t rt = 0; rt < row_tiles; ++rt) {
+    const uint64_t* kn = kop + ((uint64_t)(rt + 1) * steps) * 64u;
+#pragma unroll
+    for (int st = 0; st < SMAX; ++st)
+      knext[st] = (rt + 1 < row_tiles && (uint32_t)st < steps) ? kn[(uint64_t)st * 64u] : 0;
+    bconv_v16i acc = {};
+#pragma unroll
+    for (int st = 0; st < SMAX; ++st) {
+      if ((uint32_t)st < steps)
+        acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)kcur[st], (long)z[st], acc, 0, 0, 0);
+    }
+    // acc[4 j' + c4] = D_(4h + c4) of output J = 4 rt + j' for this coefficient.
+#pragma unroll
+    for (int jp = 0; jp < 4; ++jp) {
+      const uint32_t J = 4u * rt + jp;
+      double part = 0.0;
+      if (J < a.M) {
+        const double p = a.fp[2 * J];
+        const double* om = a.om + 16 * (uint64_t)J + 8 * h;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4)
+          part += f64_mulmod_pre((double)acc[4 * jp + c4], om[2 * c4], om[2 * c4 + 1], p);
+      }
+      const double sum = part + __shfl_xor(part, 32);
+      if (J < a.M && (uint32_t)(jp >> 1) == h) {
+        const double p = a.fp[2 * J], pinv = a.fp[2 * J + 1];
+        double r = __builtin_fma(-__builtin_rint(sum * pinv), p, sum);
+        r = r < 0.0 ? r + p : r;
+        r = r >= p ? r - p : r;
+        y[(uint64_t)J << a.log_n] = (W)(uint64_t)r;
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < SMAX; ++st) kcur[st] = knext[st];
+  }
+}
+
 template <class W>
-static hipError_t launch_bconv(const BconvArgs& a, bool f64, hipStream_t s) {
+static hipError_t launch_bconv(const BconvArgs& a, bool f64, bool mfma, hipStream_t s) {
+  if (mfma) {
+    const uint32_t tiles = a.total / 32u;  // N >= 32: tiles never straddle polynomials
+    LaunchTimer t("bconv_mfma", sizeof(W) == 4 ? "u32" : "u64", (int)a.log_n, false, false,
+                  (uint64_t)a.total * a.M, s);
+    const dim3 grid((tiles + 3u) / 4u), block(256);
+    const uint32_t steps = (a.L + 1u) / 2u;
+    if (steps <= 8) hipLaunchKernelGGL((bconv_mfma_kernel<W, 8>), grid, block, 0, s, a);
+    else if (steps <= 12) hipLaunchKernelGGL((bconv_mfma_kernel<W, 12>), grid, block, 0, s, a);
+    else if (steps <= 16) hipLaunchKernelGGL((bconv_mfma_kernel<W, 16>), grid, block, 0, s, a);
+    else if (steps <= 20) hipLaunchKernelGGL((bconv_mfma_kernel<W, 20>), grid, block, 0, s, a);
+    else if (steps <= 24) hipLaunchKernelGGL((bconv_mfma_kernel<W, 24>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((bconv_mfma_kernel<W, 32>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   const uint32_t blocks = (uint32_t)(((uint64_t)a.total + kBconvBlock - 1) / kBconvBlock);
   LaunchTimer t(f64 ? "bconv_f64" : "bconv", sizeof(W) == 4 ? "u32" : "u64", (int)a.log_n, false,
                 false, (uint64_t)a.total * a.M, s);
@@ -180,6 +292,8 @@ static void free_bconv(ntt_bconv_s* h) {
   if (h->d_f1) (void)hipFree(h->d_f1);
   if (h->d_f2) (void)hipFree(h->d_f2);
   if (h->d_fp) (void)hipFree(h->d_fp);
+  if (h->d_kop) (void)hipFree(h->d_kop);
+  if (h->d_om) (void)hipFree(h->d_om);
   delete h;
 }
 
@@ -189,9 +303,19 @@ using namespace nttk;
 
 extern "C" {
 
+// Balanced base-256 digit c (c < 7) of v < 2^50 as an int8 bit pattern; digit 7 is 0.
+static uint8_t digit256(uint64_t v, uint32_t c) {
+  const uint64_t z = (v + kDigitOffset) ^ kDigitOffset;
+  return (uint8_t)(z >> (8 * c));
+}
+
 ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
-                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits) {
+                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits,
+                            uint32_t flags) {
   clear_error();
+  if (flags & ~(NTT_BCONV_NO_MFMA | NTT_BCONV_MFMA)) return fail(NTT_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & NTT_BCONV_NO_MFMA) && (flags & NTT_BCONV_MFMA))
+    return fail(NTT_EINVAL, "NTT_BCONV_NO_MFMA and NTT_BCONV_MFMA are exclusive");
   if (!out || !src_moduli || !dst_moduli) return fail(NTT_EINVAL, "null argument");
   *out = nullptr;
   if (N < 2 || N > (1u << 16) || (N & (N - 1)))
@@ -275,6 +399,45 @@ ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_mo
     if (e == hipSuccess) e = hipMemcpy(h->d_f2, f2.data(), f2.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_fp, fp.data(), fp.size() * 8, hipMemcpyHostToDevice);
   }
+  // The matrix cores pay off for dense conversions (measured: 36 -> 36 limbs on
+  // one 2^16 polynomial 50 us against 173 us on the vector units); with fewer
+  // than 16 source or target moduli the vector form is faster.
+  h->mfma = h->f64 && N >= 32 && !(flags & NTT_BCONV_NO_MFMA) &&
+            ((flags & NTT_BCONV_MFMA) || (L >= 16 && M >= 16));
+  if (h->mfma && e == hipSuccess) {
+    // Constant operands: for row tile rt (outputs 4 rt .. 4 rt + 3), k-step s
+    // (limbs 2s, 2s + 1) and lane l, byte e of the operand is digit c = l mod 8
+    // of (Q/q_i mod p_J) 256^e mod p_J, J = 4 rt + (l mod 32) / 8, i = 2s + l / 32.
+    const uint32_t steps = (L + 1) / 2, row_tiles = (M + 3) / 4;
+    std::vector<uint64_t> kop((size_t)row_tiles * steps * 64, 0);
+    for (uint32_t rt = 0; rt < row_tiles; ++rt)
+      for (uint32_t st = 0; st < steps; ++st)
+        for (uint32_t l = 0; l < 64; ++l) {
+          const uint32_t J = 4 * rt + (l % 32) / 8, c = l % 8, i = 2 * st + l / 32;
+          if (J >= M || i >= L) continue;
+          const uint64_t p = dst_moduli[J], m = c2[2 * ((size_t)i * M + J)];
+          uint64_t word = 0, scaled = m;  // scaled = m 256^e mod p
+          for (uint32_t e8 = 0; e8 < 7; ++e8) {
+            word |= (uint64_t)digit256(scaled, c) << (8 * e8);
+            scaled = nt_mul(scaled, 256 % p, p);
+          }
+          kop[((size_t)rt * steps + st) * 64 + l] = word;
+        }
+    std::vector<double> om((size_t)M * 16);
+    for (uint32_t j = 0; j < M; ++j) {
+      const uint64_t p = dst_moduli[j];
+      uint64_t w = 1 % p;
+      for (uint32_t c = 0; c < 8; ++c) {
+        om[16 * (size_t)j + 2 * c] = (double)w;
+        om[16 * (size_t)j + 2 * c + 1] = (double)w * (1.0 / (double)p);
+        w = nt_mul(w, 256 % p, p);
+      }
+    }
+    e = hipMalloc(&h->d_kop, kop.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&h->d_om, om.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(h->d_kop, kop.data(), kop.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_om, om.data(), om.size() * 8, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     free_bconv(h);
     return hip_fail(e, "basis conversion constants");
@@ -305,13 +468,15 @@ ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, v
   a.f1 = h->d_f1;
   a.f2 = h->d_f2;
   a.fp = h->d_fp;
+  a.kop = h->d_kop;
+  a.om = h->d_om;
   a.L = h->L;
   a.M = h->M;
   a.log_n = h->log_n;
   a.total = (uint32_t)((uint64_t)batch << h->log_n);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const hipError_t e = h->word_bits == 32 ? launch_bconv<uint32_t>(a, h->f64, s)
-                                          : launch_bconv<uint64_t>(a, h->f64, s);
+  const hipError_t e = h->word_bits == 32 ? launch_bconv<uint32_t>(a, h->f64, h->mfma, s)
+                                          : launch_bconv<uint64_t>(a, h->f64, h->mfma, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return NTT_OK;
 }

@@ -74,3 +74,34 @@ def test_bconv_rejects_bad_arguments():
     with pytest.raises(ntt.NTTError) as ei:
         conv(alias, buf)
     assert ei.value.name == "NTT_EINVAL"
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("L,M", [(1, 1), (2, 4), (9, 17), (36, 36), (64, 5)])
+def test_bconv_matrix_core_form_equals_vector_form(word_bits, L, M):
+    """With every modulus below 2^50 and N >= 32 the conversion runs on the int8
+    matrix cores; it gives the vector form's words and the oracle's."""
+    if word_bits == 32:
+        pool = synth.primes_below(1 << 32, 1 << 17, L + M)
+    else:
+        pool = synth.primes_below(1 << 50, 1 << 17, L + M)
+    src, dst = pool[:L], pool[L:]
+    N = 1 << 12
+    x = synth.uniform_poly(90 + L, src, 3, N)
+    mf = _run(ntt.BasisConversion(N, src, dst, word_bits, mfma=True), x, M, word_bits)
+    vec = _run(ntt.BasisConversion(N, src, dst, word_bits, mfma=False), x, M, word_bits)
+    assert np.array_equal(mf, vec)
+    assert np.array_equal(mf[:, :, :512], oracle.bconv(x[:, :, :512], src, dst))
+
+
+def test_bconv_matrix_core_form_at_n_32_and_edge_values():
+    """N = 32 (one tile per polynomial) and residues at 0 and q - 1."""
+    pool = synth.primes_below(1 << 50, 1 << 17, 11)
+    src, dst = pool[:5], pool[5:]
+    N = 32
+    x = synth.uniform_poly(95, src, 4, N)
+    x[0] = 0
+    for i, q in enumerate(src):
+        x[1, i] = q - 1
+    got = _run(ntt.BasisConversion(N, src, dst, 64, mfma=True), x, 6, 64)
+    assert np.array_equal(got, oracle.bconv(x, src, dst))
