@@ -188,8 +188,7 @@ constexpr uint64_t kDigitOffset = 0x808080808080ull;  // 128 at digits 0..5
 
 // One wave per 32 coefficients of one polynomial (N >= 32); four waves per block.
 // SMAX bounds the k-steps (two limbs each) so that the digit words and two sets
-// of constant operands stay in registers: the operands of row tile rt + 1 are
-// requested before the products of row tile rt, hiding their L2 latency.
+// of constant operands stay in registers.
 template <class W, int SMAX>
 __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
@@ -218,43 +217,59 @@ __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
   W* y = static_cast<W*>(a.out) + ((b * a.M) << a.log_n) + n;
   const uint32_t row_tiles = (a.M + 3u) >> 2;
   const uint64_t* kop = a.kop + lane;
-  uint64_t kcur[SMAX], knext[SMAX];
+  // Indices are clamped into the table, so no load can leave it whatever the
+  // compiler hoists; the unused words are zeroed.
+  auto load_k = [&](uint64_t (&k)[SMAX], uint32_t rt) {
+    const uint32_t rc = rt < row_tiles ? rt : row_tiles - 1u;
+    const uint64_t* kr = kop + ((uint64_t)rc * steps) * 64u;
 #pragma unroll
-  for (int st = 0; st < SMAX; ++st) kcur[st] = (uint32_t)st < steps ? kop[(uint64_t)st * 64u] : 0;
-  for (uint32_t rt = 0; rt < row_tiles; ++rt) {
-    const uint64_t* kn = kop + ((uint64_t)(rt + 1) * steps) * 64u;
-#pragma unroll
-    for (int st = 0; st < SMAX; ++st)
-      knext[st] = (rt + 1 < row_tiles && (uint32_t)st < steps) ? kn[(uint64_t)st * 64u] : 0;
+    for (int st = 0; st < SMAX; ++st) {
+      const uint32_t sc = (uint32_t)st < steps ? (uint32_t)st : steps - 1u;
+      if (rt < row_tiles && (uint32_t)st < steps) k[st] = kr[(uint64_t)sc * 64u];
+      else k[st] = 0;
+    }
+  };
+  auto products = [&](const uint64_t (&k)[SMAX]) {
     bconv_v16i acc = {};
 #pragma unroll
     for (int st = 0; st < SMAX; ++st) {
       if ((uint32_t)st < steps)
-        acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)kcur[st], (long)z[st], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)k[st], (long)z[st], acc, 0, 0, 0);
     }
+    return acc;
+  };
+  // Pipeline: the products of row tile rt + 1 and the operand loads of rt + 2
+  // are issued before the vector work that finishes row tile rt.
+  uint64_t ka[SMAX], kb[SMAX];
+  load_k(ka, 0);
+  bconv_v16i acc = products(ka);
+  load_k(kb, 1);
+  for (uint32_t rt = 0; rt < row_tiles; ++rt) {
+    bconv_v16i acc2 = {};
+    if (rt + 1 < row_tiles) acc2 = products(kb);
+    load_k(ka, rt + 2);
     // acc[4 j' + c4] = D_(4h + c4) of output J = 4 rt + j' for this coefficient.
 #pragma unroll
     for (int jp = 0; jp < 4; ++jp) {
       const uint32_t J = 4u * rt + jp;
+      const uint32_t Jc = J < a.M ? J : a.M - 1u;  // in-table index for rows past M
+      const double* om = a.om + 16 * (uint64_t)Jc + 8 * h;
+      const double p = a.fp[2 * Jc], pinv = a.fp[2 * Jc + 1];
       double part = 0.0;
-      if (J < a.M) {
-        const double p = a.fp[2 * J];
-        const double* om = a.om + 16 * (uint64_t)J + 8 * h;
 #pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4)
-          part += f64_mulmod_pre((double)acc[4 * jp + c4], om[2 * c4], om[2 * c4 + 1], p);
-      }
+      for (int c4 = 0; c4 < 4; ++c4)
+        part += f64_mulmod_pre((double)acc[4 * jp + c4], om[2 * c4], om[2 * c4 + 1], p);
       const double sum = part + __shfl_xor(part, 32);
       if (J < a.M && (uint32_t)(jp >> 1) == h) {
-        const double p = a.fp[2 * J], pinv = a.fp[2 * J + 1];
         double r = __builtin_fma(-__builtin_rint(sum * pinv), p, sum);
         r = r < 0.0 ? r + p : r;
         r = r >= p ? r - p : r;
         y[(uint64_t)J << a.log_n] = (W)(uint64_t)r;
       }
     }
+    acc = acc2;
 #pragma unroll
-    for (int st = 0; st < SMAX; ++st) kcur[st] = knext[st];
+    for (int st = 0; st < SMAX; ++st) kb[st] = ka[st];
   }
 }
 
