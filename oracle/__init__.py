@@ -311,3 +311,41 @@ def bconv(x, src_moduli, dst_moduli) -> np.ndarray:
         lib.orc_bconv(_p(yb), _p(xb), N, _p(src), L, _p(dst), M)
         out[b] = yb
     return out.reshape(a.shape[:-2] + (M, N))
+
+
+# -- one batched CMux step of blind rotation (Sec. II-B, Sec. IV-A) -------------------
+
+def monomial_mul(a, moduli, rot) -> np.ndarray:
+    """X^rot[g] * a[g] in Z_q[x]/(x^N+1) for a[num][comps][L][N] (rot[g] taken mod 2N):
+    the term a_i x^i becomes a_i x^(i + r), negated each time the exponent passes N."""
+    x = _u64(a)
+    mod = [int(q) for q in np.atleast_1d(moduli)]
+    num, comps, L, N = x.shape
+    out = np.empty_like(x)
+    for g in range(num):
+        r = int(rot[g]) % (2 * N)
+        for l in range(L):
+            q = mod[l]
+            for c in range(comps):
+                row = [int(v) for v in x[g, c, l]]
+                res = [0] * N
+                for i, v in enumerate(row):
+                    e = (i + r) % (2 * N)
+                    if e < N:
+                        res[e] = (res[e] + v) % q
+                    else:
+                        res[e - N] = (res[e - N] - v) % q
+                out[g, c, l] = np.array(res, dtype=np.uint64)
+    return out
+
+
+def cmux(acc, key, moduli, rot, levels: int, log_base: int) -> np.ndarray:
+    """out[g] = acc[g] + ExtProd(key, X^rot[g] acc[g] - acc[g]): the external product
+    of the gadget digits of the rotated difference with the RGSW key
+    key[comps*levels][comps][L][N] (transform domain), added back to acc."""
+    x = _u64(acc)
+    mod = np.atleast_1d(moduli).astype(np.uint64)
+    rotated = monomial_mul(x, moduli, rot)
+    diff = (rotated + (mod[None, None, :, None] - x)) % mod[None, None, :, None]
+    prod = external_product_decomposed(diff, key, moduli, levels, log_base, x.shape[1])
+    return (prod + x) % mod[None, None, :, None]

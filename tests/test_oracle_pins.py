@@ -479,3 +479,48 @@ def test_bconv_small_values_are_exact_and_sum_is_explicit():
     assert not z.any()
     one = oracle.bconv(x[:, :1], src[:1], dst)
     assert [[int(v) for v in r] for r in one[0]] == [[int(v) % p for v in x[0, 0]] for p in dst]
+
+
+# -- batched CMux ---------------------------------------------------------------------
+
+def test_monomial_mul_matches_schoolbook_with_a_monomial():
+    q, N = 4294957057, 16
+    rng = random.Random(40)
+    a = np.array([[[[rng.randrange(q) for _ in range(N)]]] for _ in range(3)], dtype=np.uint64)
+    rots = [0, 5, 2 * N - 3]
+    got = oracle.monomial_mul(a, [q], rots)
+    for g, r in enumerate(rots):
+        mono = [0] * N
+        if r < N:
+            mono[r] = 1
+        else:
+            mono[r - N] = q - 1  # x^r = -x^(r-N)
+        want = py_ref.negacyclic_schoolbook([int(v) for v in a[g, 0, 0]], mono, q)
+        assert [int(v) for v in got[g, 0, 0]] == want
+
+
+def _noise_free_rgsw_of_bit(bit, q, N, comps, levels, log_base):
+    """key[c*levels + j][col] = bit * B^j on the diagonal col == c (transform domain):
+    a gadget encryption of `bit` without mask or noise."""
+    key = np.zeros((comps * levels, comps, 1, N), dtype=np.uint64)
+    for c in range(comps):
+        for j in range(levels):
+            poly = np.zeros(N, dtype=np.uint64)
+            poly[0] = (bit * pow(2, log_base * j, q)) % q
+            key[c * levels + j, c, 0] = oracle.forward(poly, [q])
+    return key
+
+
+@pytest.mark.parametrize("bit", [0, 1])
+def test_cmux_with_a_noise_free_key_selects(bit):
+    """With the gadget encryption of a bit b and no noise, acc + ExtProd(key, X^a acc - acc)
+    is exactly X^(a b) acc: the CMux picks the rotated or the unrotated accumulator."""
+    q, N, comps, levels, lb = 4294957057, 32, 2, 3, 11
+    rng = random.Random(41 + bit)
+    acc = np.array([[[[rng.randrange(q) for _ in range(N)]] for _ in range(comps)] for _ in range(4)],
+                   dtype=np.uint64)
+    rots = [0, 3, N, 2 * N - 1]
+    key = _noise_free_rgsw_of_bit(bit, q, N, comps, levels, lb)
+    out = oracle.cmux(acc, key, [q], rots, levels, lb)
+    want = oracle.monomial_mul(acc, [q], rots) if bit else acc
+    assert np.array_equal(out, want)
