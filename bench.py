@@ -295,10 +295,19 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
     def c3_decomposed():
         p3.external_product_decomposed(acc3, ct, key4, 3, 11, stream)
 
+    # One batched CMux step of blind rotation over the same ciphertexts:
+    # acc + ExtProd(key, X^a acc - acc), a different rotation per ciphertext.
+    rot3 = torch.tensor([(37 * g + 11) % (2 * N) for g in range(G)], dtype=torch.int32, device="cuda")
+    cm_out = empty_device((G, 2, 1, N), 32)
+
+    def c3_cmux():
+        p3.cmux(cm_out, ct, rot3, key4, 3, 11, stream)
+
     tb = _time(torch, c3_batched, 20, stream)
     tp = _time(torch, c3_plain, 3, stream)
     tf = _time(torch, c3_fused, 20, stream)
     td = _time(torch, c3_decomposed, 20, stream)
+    tcm = _time(torch, c3_cmux, 20, stream)
     copy_ms = _time(torch, lambda: work.copy_(a), 20, stream)
     torch.cuda.synchronize()
     n3 = Pn + G * cols
@@ -311,7 +320,9 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
                       "external_product_same_words": bool(torch.equal(acc, acc2)),
                       "decomposed_ciphertexts": G,
                       "external_product_decomposed_us": round(td * 1e3, 2),
-                      "external_product_decomposed_ntt_per_s": (G * rows + G * cols) / (td * 1e-3)}
+                      "external_product_decomposed_ntt_per_s": (G * rows + G * cols) / (td * 1e-3),
+                      "cmux_step_us": round(tcm * 1e3, 2),
+                      "cmux_per_s": G / (tcm * 1e-3)}
     # C1 latency: one 2^10 forward + inverse, u32.
     q1 = synth.c1_prime(0)
     p1 = ntt.Plan(N, [q1], 32)

@@ -227,6 +227,25 @@ ntt_status ntt_external_product_decomposed(ntt_plan_t plan, void* out, const voi
                                            uint32_t levels, uint32_t log_base, uint32_t cols,
                                            void* stream);
 
+/* One batched CMux step of blind rotation (Sec. II-B: the accumulator goes
+ * through n_lwe CMux gates against RGSW bootstrapping keys; Sec. IV-A: all
+ * ciphertexts of one key bit in one batched gate).  For every ciphertext g,
+ *   out[g] = acc[g] + ExtProd(key, X^rot[g] acc[g] - acc[g])
+ * where X^r acc is the negacyclic monomial product (r taken mod 2N) and ExtProd
+ * is the external product of ntt_external_product_decomposed (gadget digits of
+ * each component, rows c * levels + j, columns = comps).
+ *   acc   [num_ct][comps][L][N], natural order, not modified
+ *   rot   device array of num_ct rotation amounts
+ *   key   [comps * levels][comps][L][N], transform domain (the RGSW key)
+ *   out   [num_ct][comps][L][N]; must not alias acc or key
+ * Digit and size rules as ntt_external_product_decomposed.  For N <= 2^12 one
+ * launch per class rotates, decomposes, transforms, multiplies-and-accumulates,
+ * inverse-transforms and adds; other shapes go through a stream-ordered
+ * workspace. */
+ntt_status ntt_cmux(ntt_plan_t plan, void* out, const void* acc, const uint32_t* rot,
+                    const void* key, uint32_t num_ct, uint32_t comps, uint32_t levels,
+                    uint32_t log_base, void* stream);
+
 /* Negacyclic product c = a * b mod (x^N + 1) per limb, through Eq. (1):
  * out, a, b are [batch][L][N] in natural order; a and b are not modified;
  * out must not alias a or b.  A two-pass product (N above the single-pass

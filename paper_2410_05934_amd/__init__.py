@@ -71,6 +71,7 @@ _SIGS = {
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_cmux": [_vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp],
     "ntt_bconv_create": [ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u64), _u32, ctypes.POINTER(_u64),
                          _u32, _u32, _u32],
     "ntt_bconv": [_vp, _vp, _vp, _u32, _vp],
@@ -523,6 +524,24 @@ class Plan:
                                                      key.data_ptr(), num_ct, comps, levels,
                                                      log_base, cols, _stream_handle(stream)),
                "ntt_external_product_decomposed")
+        return out
+
+    def cmux(self, out, acc, rot, key, levels: int, log_base: int, stream=None):
+        """out[g] = acc[g] + ExtProd(key, X^rot[g] acc[g] - acc[g]); acc/out
+        [num_ct][comps][L][N], rot a device uint32 (int32) tensor of num_ct amounts,
+        key [comps*levels][comps][L][N] in the transform domain."""
+        if acc.dim() != 4 or key.dim() != 4 or out.shape != acc.shape:
+            raise ValueError("acc/out are [num_ct][comps][L][N], key [comps*levels][comps][L][N]")
+        num_ct, comps = int(acc.shape[0]), int(acc.shape[1])
+        if tuple(key.shape[:2]) != (comps * levels, comps):
+            raise ValueError("key must be [comps*levels][comps][L][N]")
+        if not rot.is_cuda or rot.element_size() != 4 or rot.numel() != num_ct or not rot.is_contiguous():
+            raise ValueError("rot must be a contiguous device tensor of num_ct 32-bit amounts")
+        for t, name in ((acc, "acc"), (key, "key"), (out, "out")):
+            self._batch_of(t, name)
+        _check(lib().ntt_cmux(self._h, out.data_ptr(), acc.data_ptr(), rot.data_ptr(),
+                              key.data_ptr(), num_ct, comps, levels, log_base,
+                              _stream_handle(stream)), "ntt_cmux")
         return out
 
     def automorph(self, out, a, k: int, transformed: bool = False, stream=None):

@@ -351,12 +351,15 @@ hipError_t launch_xprod_n(const XpArgs& x, uint32_t groups, hipStream_t s) {
   using S = RowShape<LOGN2, 4>;
   const uint32_t threads = x.rows * S::TPC;
   const size_t lds = (size_t)x.rows * ((1u << LOGN2) + (1u << LOGN2) / 16) * sizeof(typename A::V);
-  LaunchTimer t(x.levels ? "xprod_dec" : "xprod", A::kName, LOGN2, false, false,
+  LaunchTimer t(x.rot ? "cmux" : x.levels ? "xprod_dec" : "xprod", A::kName, LOGN2, false, false,
                 ((uint64_t)groups * x.cols * x.n_cls) << LOGN2, s);
-  if (x.levels)
-    hipLaunchKernelGGL((xprod_kernel<A, LOGN2, true>), dim3(groups * x.n_cls), dim3(threads), lds, s, x);
+  const dim3 grid(groups * x.n_cls), block(threads);
+  if (x.rot)
+    hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpCmux>), grid, block, lds, s, x);
+  else if (x.levels)
+    hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpDecompose>), grid, block, lds, s, x);
   else
-    hipLaunchKernelGGL((xprod_kernel<A, LOGN2>), dim3(groups * x.n_cls), dim3(threads), lds, s, x);
+    hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpOperands>), grid, block, lds, s, x);
   return hipGetLastError();
 }
 
@@ -365,8 +368,10 @@ hipError_t launch_xprod_n(const XpArgs& x, uint32_t groups, hipStream_t s) {
 template <class A>
 hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                      uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s,
-                     uint32_t comps = 0, uint32_t levels = 0, uint32_t log_base = 0) {
+                     uint32_t comps = 0, uint32_t levels = 0, uint32_t log_base = 0,
+                     const uint32_t* rot = nullptr) {
   XpArgs x;
+  x.rot = rot;
   x.comps = comps;
   x.levels = levels;
   x.log_base = log_base;

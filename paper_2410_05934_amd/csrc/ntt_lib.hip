@@ -172,7 +172,7 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
 template <class A>
 hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                      uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s,
-                     uint32_t comps, uint32_t levels, uint32_t log_base);
+                     uint32_t comps, uint32_t levels, uint32_t log_base, const uint32_t* rot);
 #define NTT_EXTERN_CLASS(A)                                                                   \
   extern template hipError_t transform_cls<A>(const ntt_plan_s*, int, void*, uint32_t, bool,  \
                                               uint32_t, uint32_t*, hipStream_t);              \
@@ -185,7 +185,7 @@ hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const
                                         const void*, uint32_t, uint32_t, uint32_t, hipStream_t); \
   extern template hipError_t xprod_cls<A>(const ntt_plan_s*, int, void*, const void*,         \
                                           const void*, uint32_t, uint32_t, uint32_t, hipStream_t, \
-                                          uint32_t, uint32_t, uint32_t);
+                                          uint32_t, uint32_t, uint32_t, const uint32_t*);
 NTT_EXTERN_CLASS(ArF64S)
 NTT_EXTERN_CLASS(ArF64L)
 NTT_EXTERN_CLASS(ArI64)
@@ -230,6 +230,48 @@ static __global__ void __launch_bounds__(256) decompose_kernel(DecArgs d) {
   const uint32_t j = r - comp * d.levels;
   const W x = static_cast<const W*>(d.ct)[((((uint64_t)g * d.comps + comp) * d.L + l) << d.log_n) + n];
   static_cast<W*>(d.out)[e] = signed_digit<W>(x, j, d.levels, d.log_base, d.offset, d.limbs[l].q);
+}
+
+// X^rot[g] acc[g] - acc[g] for acc [num_ct][comps][L][N] (rot taken mod 2N).
+struct RotArgs {
+  void* out;
+  const void* acc;
+  const uint32_t* rot;
+  const LimbDev* limbs;
+  uint32_t L, log_n, comps;
+  uint32_t total;  // words, < 2^32
+};
+
+template <class W>
+static __global__ void __launch_bounds__(256) rotdiff_kernel(RotArgs d) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= d.total) return;
+  const uint32_t nmask = (1u << d.log_n) - 1u;
+  const uint32_t pos = e & nmask;
+  const uint32_t row = e >> d.log_n;  // (g * comps + c) * L + l
+  const uint32_t l = row % d.L;
+  const uint32_t g = row / d.L / d.comps;
+  const uint64_t q = d.limbs[l].q;
+  const W* src = static_cast<const W*>(d.acc) + ((uint64_t)row << d.log_n);
+  uint32_t r = d.rot[g] & (2u * nmask + 1u);
+  const bool flip = r > nmask;
+  r &= nmask;
+  const bool wrap = pos < r;
+  const uint64_t rv = (uint64_t)src[(pos - r) & nmask], av = (uint64_t)src[pos];
+  const uint64_t sv = (flip != wrap) ? (rv == 0 ? 0 : q - rv) : rv;
+  static_cast<W*>(d.out)[e] = (W)(sv >= av ? sv - av : sv + q - av);
+}
+
+// out += acc elementwise mod q (same [num][comps][L][N] layout).
+template <class W>
+static __global__ void __launch_bounds__(256) addmod_kernel(RotArgs d) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= d.total) return;
+  const uint32_t l = (e >> d.log_n) % d.L;
+  const uint64_t q = d.limbs[l].q;
+  W* o = static_cast<W*>(d.out);
+  const uint64_t s2 = (uint64_t)o[e] + (uint64_t)static_cast<const W*>(d.acc)[e];
+  o[e] = (W)(s2 >= q ? s2 - q : s2);
 }
 
 static __global__ void fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
@@ -453,7 +495,8 @@ ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const
     return fail(NTT_EINVAL, "out and key must each hold < 2^32 words");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (xprod_fits(plan, rows, cols, key)) {
-    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s, 0u, 0u, 0u)));
+    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s, 0u, 0u, 0u,
+                                        nullptr)));
     return NTT_OK;
   }
   // Other shapes: forward a copy of the operands, MAC, inverse.
@@ -499,7 +542,8 @@ ntt_status ntt_external_product_decomposed(ntt_plan_t plan, void* out, const voi
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (xprod_fits(plan, (uint32_t)rows, cols, key)) {
     NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, ct, key, (uint32_t)rows, cols,
-                                        (uint32_t)num_operands, s, comps, levels, log_base)));
+                                        (uint32_t)num_operands, s, comps, levels, log_base,
+                                        nullptr)));
     return NTT_OK;
   }
   // Other shapes: the digits into a stream-ordered workspace, then the external
@@ -529,6 +573,69 @@ ntt_status ntt_external_product_decomposed(ntt_plan_t plan, void* out, const voi
   if (e != hipSuccess) st = hip_fail(e, "kernel launch");
   if (st == NTT_OK) st = ntt_external_product(plan, out, ws, key, (uint32_t)rows, cols,
                                               (uint32_t)num_operands, stream);
+  (void)hipFreeAsync(ws, s);
+  return st;
+}
+
+ntt_status ntt_cmux(ntt_plan_t plan, void* out, const void* acc, const uint32_t* rot,
+                    const void* key, uint32_t num_ct, uint32_t comps, uint32_t levels,
+                    uint32_t log_base, void* stream) {
+  clear_error();
+  if (!plan) return fail(NTT_EINVAL, "null plan");
+  if (!out || !acc || !rot || !key) return fail(NTT_EINVAL, "null data");
+  if (num_ct == 0 || comps == 0 || levels == 0)
+    return fail(NTT_EINVAL, "num_ct, comps and levels must be >= 1");
+  if (log_base == 0 || log_base > 32) return fail(NTT_EINVAL, "log_base=%u not in 1..32", log_base);
+  if (out == acc || out == key) return fail(NTT_EINVAL, "out must not alias acc or key");
+  const uint64_t span = (uint64_t)levels * log_base;
+  if (span > 64) return fail(NTT_EINVAL, "levels * log_base = %llu exceeds 64", (unsigned long long)span);
+  for (uint32_t l = 0; l < plan->L; ++l) {
+    if (span < 64 && plan->moduli[l] > (1ull << (span - 1)))
+      return fail(NTT_EINVAL, "levels * log_base = %llu too small for q=%llu",
+                  (unsigned long long)span, (unsigned long long)plan->moduli[l]);
+  }
+  const uint64_t rows = (uint64_t)comps * levels;
+  const uint64_t poly = (uint64_t)plan->L << plan->log_n;
+  const uint64_t acc_words = (uint64_t)num_ct * comps * poly;
+  if ((uint64_t)num_ct * rows * poly >= (1ull << 32) || rows * comps * poly >= (1ull << 32))
+    return fail(NTT_EINVAL, "operands and key must each hold < 2^32 words");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (xprod_fits(plan, (uint32_t)rows, comps, key)) {
+    NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, acc, key, (uint32_t)rows, comps,
+                                        (uint32_t)(num_ct * rows), s, comps, levels, log_base,
+                                        rot)));
+    return NTT_OK;
+  }
+  // Other shapes: the rotated difference into a workspace, its decomposed
+  // external product into out, then out += acc.
+  const size_t bytes = (size_t)acc_words * (plan->word_bits / 8);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, bytes, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(CMux workspace)");
+  RotArgs d;
+  d.out = ws;
+  d.acc = acc;
+  d.rot = rot;
+  d.limbs = plan->d_limbs;
+  d.L = plan->L;
+  d.log_n = plan->log_n;
+  d.comps = comps;
+  d.total = (uint32_t)acc_words;
+  const uint32_t blocks = (uint32_t)(((uint64_t)d.total + 255) / 256);
+  if (plan->word_bits == 32) hipLaunchKernelGGL(rotdiff_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s, d);
+  else hipLaunchKernelGGL(rotdiff_kernel<uint64_t>, dim3(blocks), dim3(256), 0, s, d);
+  e = hipGetLastError();
+  ntt_status st = e == hipSuccess ? NTT_OK : hip_fail(e, "kernel launch");
+  if (st == NTT_OK)
+    st = ntt_external_product_decomposed(plan, out, ws, key, num_ct, comps, levels, log_base,
+                                         comps, stream);
+  if (st == NTT_OK) {
+    d.out = out;
+    if (plan->word_bits == 32) hipLaunchKernelGGL(addmod_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s, d);
+    else hipLaunchKernelGGL(addmod_kernel<uint64_t>, dim3(blocks), dim3(256), 0, s, d);
+    e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(e, "kernel launch");
+  }
   (void)hipFreeAsync(ws, s);
   return st;
 }

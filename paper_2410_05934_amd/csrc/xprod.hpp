@@ -30,14 +30,25 @@ struct XpArgs {
   uint32_t rows, cols, num_operands;
   uint32_t comps, levels, log_base;  // decomposing: rows = comps * levels
   uint64_t dec_offset;               // digit_offset(levels, log_base)
+  const uint32_t* rot;               // CMux: rotation of each ciphertext (taken mod 2N)
+};
+
+// What the kernel's operands are.
+enum XpMode : int {
+  kXpOperands = 0,  // the operands themselves, in `a`
+  kXpDecompose = 1, // the gadget digits of the ciphertexts in `a`
+  kXpCmux = 2,      // the digits of X^rot acc - acc (acc in `a`); acc is added to the result
 };
 
 // Grid: groups * n_cls workgroups of rows * (N/16) threads; dynamic LDS of
 // rows regions of N + N/16 values (the padded chunk, also for N = 16 where the
 // row pass itself needs no LDS).  Requires cols <= rows.
-// DEC: the operands are not in memory; slot s = c * levels + j computes digit j
-// of component c of ciphertext `grp` as it loads (Decompose, fused).
-template <class A, int LOGN2, bool DEC = false>
+// kXpDecompose: the operands are not in memory; slot s = c * levels + j computes
+// digit j of component c of ciphertext `grp` as it loads (Decompose, fused).
+// kXpCmux: one CMux of blind rotation (Sec. II-B, Sec. IV-A): the digits are
+// those of X^r acc - acc (r = rot[grp]), and the stored result is acc plus the
+// inverse transform, i.e. acc + ExtProd(key, X^r acc - acc); cols = comps.
+template <class A, int LOGN2, int MODE = kXpOperands>
 __global__ void __launch_bounds__(1024)
 xprod_kernel(XpArgs args) {
   constexpr int RB = 4;
@@ -84,7 +95,7 @@ xprod_kernel(XpArgs args) {
   // transforms the group's first operand and its result is never read).
   const uint32_t op = slot < nr ? slot : 0;
   V v[R];
-  if constexpr (DEC) {
+  if constexpr (MODE == kXpDecompose) {
     const uint32_t comp = op / args.levels;
     const uint32_t digit = op - comp * args.levels;
     const W* src = reinterpret_cast<const W*>(args.a) +
@@ -93,6 +104,29 @@ xprod_kernel(XpArgs args) {
     for (int u = 0; u < R; ++u)
       v[u] = ar.from_word(signed_digit<W>(src[ins_bits<RB>(tt, u, H0)], digit, args.levels,
                                           args.log_base, args.dec_offset, ld.q));
+  } else if constexpr (MODE == kXpCmux) {
+    const uint32_t comp = op / args.levels;
+    const uint32_t digit = op - comp * args.levels;
+    const W* src = reinterpret_cast<const W*>(args.a) +
+                   ((uint64_t)grp * args.comps + comp) * poly_words + limb_off;
+    constexpr uint32_t kN = 1u << LOGN2;
+    // X^r = -X^(r - N) for r >= N; then coefficient pos of X^r' a is a[pos - r'],
+    // negated once more when pos - r' wraps below zero.
+    uint32_t r = args.rot[grp] & (2u * kN - 1u);
+    const bool flip = r >= kN;
+    r &= kN - 1u;
+    const uint64_t q = ld.q;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t pos = ins_bits<RB>(tt, u, H0);
+      const bool wrap = pos < r;
+      const uint64_t rv = (uint64_t)src[(pos - r) & (kN - 1u)];
+      const uint64_t av = (uint64_t)src[pos];
+      const uint64_t sv = (flip != wrap) ? (rv == 0 ? 0 : q - rv) : rv;  // X^r acc at pos
+      const uint64_t dv = sv >= av ? sv - av : sv + q - av;             // minus acc
+      v[u] = ar.from_word(signed_digit<W>((W)dv, digit, args.levels, args.log_base,
+                                          args.dec_offset, q));
+    }
   } else {
     const W* src = reinterpret_cast<const W*>(args.a) + (uint64_t)(first + op) * poly_words +
                    limb_off;
@@ -147,8 +181,21 @@ xprod_kernel(XpArgs args) {
   if (slot < args.cols) {
     W* dst = reinterpret_cast<W*>(args.dst) + ((uint64_t)grp * args.cols + slot) * poly_words +
              limb_off;
+    if constexpr (MODE == kXpCmux) {
+      // acc + ExtProd: component `slot` of this ciphertext, same positions
+      const W* a0 = reinterpret_cast<const W*>(args.a) +
+                    ((uint64_t)grp * args.comps + slot) * poly_words + limb_off;
+      const uint64_t q = ld.q;
 #pragma unroll
-    for (int u = 0; u < R; ++u) dst[ins_bits<RB>(tt, u, H0)] = ar.to_word(acc[u]);
+      for (int u = 0; u < R; ++u) {
+        const uint32_t pos = ins_bits<RB>(tt, u, H0);
+        const uint64_t s2 = (uint64_t)ar.to_word(acc[u]) + (uint64_t)a0[pos];
+        dst[pos] = (W)(s2 >= q ? s2 - q : s2);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < R; ++u) dst[ins_bits<RB>(tt, u, H0)] = ar.to_word(acc[u]);
+    }
   }
 }
 
