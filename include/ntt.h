@@ -246,6 +246,15 @@ ntt_status ntt_cmux(ntt_plan_t plan, void* out, const void* acc, const uint32_t*
                     const void* key, uint32_t num_ct, uint32_t comps, uint32_t levels,
                     uint32_t log_base, void* stream);
 
+/* Forward transforms of a and b in place (as ntt_forward on each) and their
+ * elementwise product out = a (.) b (as ntt_pointwise_mul), from one pass over
+ * the rows: the row pass that finishes both transforms also writes the product,
+ * so the transformed operands are not read back.  All three [batch][L][N];
+ * a, b and out distinct (else NTT_EINVAL).  The words equal those of the
+ * separate calls. */
+ntt_status ntt_forward_mul(ntt_plan_t plan, void* out, void* a, void* b, uint32_t batch,
+                           void* stream);
+
 /* Negacyclic product c = a * b mod (x^N + 1) per limb, through Eq. (1):
  * out, a, b are [batch][L][N] in natural order; a and b are not modified;
  * out must not alias a or b.  A two-pass product (N above the single-pass

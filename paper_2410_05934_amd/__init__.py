@@ -71,6 +71,7 @@ _SIGS = {
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_forward_mul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_cmux": [_vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp],
     "ntt_bconv_create": [ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u64), _u32, ctypes.POINTER(_u64),
                          _u32, _u32, _u32],
@@ -554,6 +555,15 @@ class Plan:
         _check(lib().ntt_automorph(self._h, out.data_ptr(), a.data_ptr(), n, int(k),
                                    AUTOMORPH_TRANSFORMED if transformed else 0,
                                    _stream_handle(stream)), "ntt_automorph")
+        return out
+
+    def forward_mul(self, out, a, b, stream=None):
+        """Forward NTT of a and b in place and out = a (.) b, in one pass over the rows."""
+        n = self._batch_of(out, "out")
+        if self._batch_of(a, "a") != n or self._batch_of(b, "b") != n:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_forward_mul(self._h, out.data_ptr(), a.data_ptr(), b.data_ptr(), n,
+                                     _stream_handle(stream)), "ntt_forward_mul")
         return out
 
     def polymul(self, out, a, b, stream=None):

@@ -57,6 +57,7 @@ struct RowArgs {
   uint32_t log_n1;           // column stages before this pass (0: single pass)
   uint32_t total_chunks;     // batch * n_cls * N1
   uint32_t batch;            // polynomials
+  void* dst2;                // forward-and-multiply rows: the product a (.) b
   // When the launch's class holds one limb (n_cls == 1): that limb's index and
   // constants, so that short launches read them from their arguments instead of
   // through two dependent global loads (limb list, then constants).
@@ -575,7 +576,10 @@ row_kernel(RowArgs args) {
 // product, inverse -- Eq. (1) without leaving registers/LDS.  With TWO_PASS
 // the inputs are column-pass outputs and the result still needs the inverse
 // column pass.
-template <class A, int LOGN2, bool TWO_PASS, int RB = 4>
+// FWDMUL: forward-and-multiply rows instead: a (src, in place through dst) and b
+// (src2, in place) are written back transformed and their elementwise product
+// goes to dst2, all in the forward's output order (no inverse).
+template <class A, int LOGN2, bool TWO_PASS, int RB = 4, bool FWDMUL = false>
 __global__ void __launch_bounds__((RowShape<LOGN2, RB>::BLOCK))
 polymul_row_kernel(RowArgs args) {
   using S = RowShape<LOGN2, RB>;
@@ -609,6 +613,36 @@ polymul_row_kernel(RowArgs args) {
     vb[u] = TWO_PASS ? ar.from_raw(y) : ar.from_word(y);
   }
   row_forward2_from<A, LOGN2, RB, 0>(ar, va, vb, twf, cp.base, tt, lds);
+  if constexpr (FWDMUL) {
+    // Thread tt holds positions tt*R + u; each of the three results goes through
+    // the (free) LDS region once so that every store instruction is contiguous.
+    W* __restrict__ da = reinterpret_cast<W*>(args.dst) + cp.off;
+    W* __restrict__ db = reinterpret_cast<W*>(const_cast<void*>(args.src2)) + cp.off;
+    W* __restrict__ dp = reinterpret_cast<W*>(args.dst2) + cp.off;
+    auto put = [&](W* __restrict__ d, const V (&x)[R]) {
+      if constexpr (S::K > 1) {
+        using MB = LdsMap<RB, 0>;
+        const uint32_t bb = MB::base(tt);
+#pragma unroll
+        for (int u = 0; u < R; ++u) lds[MB::slot(tt, bb, u)] = x[u];
+        __syncthreads();
+        if (cp.valid) {
+#pragma unroll
+          for (int u = 0; u < R; ++u) d[tt + u * S::TPC] = ar.to_word(lds[S::tail_slot(tt, u)]);
+        }
+        __syncthreads();
+      } else if (cp.valid) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) d[u] = ar.to_word(x[u]);
+      }
+    };
+    put(da, va);
+    put(db, vb);
+#pragma unroll
+    for (int u = 0; u < R; ++u) va[u] = ar.mul(va[u], vb[u]);  // a is written; reuse
+    put(dp, va);
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     va[u] = ar.mul(va[u], vb[u]);

@@ -35,6 +35,17 @@ hipError_t launch_pm_n(const RowArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class A, int LOGN2, bool TWO, int RB = 4>
+hipError_t launch_fm_n(const RowArgs& a, hipStream_t s) {
+  using S = RowShape<LOGN2, RB>;
+  const uint32_t blocks = (a.total_chunks + S::CPW - 1) / S::CPW;
+  LaunchTimer t(RB == 4 ? "fwdmul_row" : "fwdmul_row8", A::kName, LOGN2, false, TWO,
+                (uint64_t)a.total_chunks << LOGN2, s);
+  hipLaunchKernelGGL((polymul_row_kernel<A, LOGN2, TWO, RB, true>), dim3(blocks), dim3(S::BLOCK), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
 template <class A, int LOGN1, bool INV, bool TWO>
 hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
   const uint64_t threads = (uint64_t)a.total_cols * (a.src2 ? 2 : 1);
@@ -137,6 +148,7 @@ inline RowArgs row_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.log_n1 = (uint32_t)n1;
   a.total_chunks = batch * p->cls_cnt[c] << n1;
   a.batch = batch;
+  a.dst2 = nullptr;
   a.limb0 = p->cls_cnt[c] == 1 ? p->h_cls_limbs[p->cls_off[c]] : 0u;
   a.one = p->h_limbs[a.limb0];
   return a;
@@ -192,6 +204,32 @@ hipError_t launch_fused_n(FusedArgs a, int device, hipStream_t s) {
                 (uint64_t)a.n_tr << (LOGN1 + 12), s);
   hipLaunchKernelGGL((fused_kernel<A, LOGN1, 12, INV, RB>), dim3(grid), dim3(S::BLOCK), 0, s, a);
   return hipGetLastError();
+}
+
+template <class A, bool TWO>
+hipError_t launch_fm(int logn2, const RowArgs& a, hipStream_t s, int rb = 4) {
+  if (rb == 3) {
+    switch (logn2) {
+      case 10: return launch_fm_n<A, 10, TWO, 3>(a, s);
+      case 11: return launch_fm_n<A, 11, TWO, 3>(a, s);
+      case 12: return launch_fm_n<A, 12, TWO, 3>(a, s);
+      case 13: return launch_fm_n<A, 13, TWO, 3>(a, s);
+      default: break;
+    }
+  }
+  switch (logn2) {
+    case 4: return launch_fm_n<A, 4, TWO>(a, s);
+    case 5: return launch_fm_n<A, 5, TWO>(a, s);
+    case 6: return launch_fm_n<A, 6, TWO>(a, s);
+    case 7: return launch_fm_n<A, 7, TWO>(a, s);
+    case 8: return launch_fm_n<A, 8, TWO>(a, s);
+    case 9: return launch_fm_n<A, 9, TWO>(a, s);
+    case 10: return launch_fm_n<A, 10, TWO>(a, s);
+    case 11: return launch_fm_n<A, 11, TWO>(a, s);
+    case 12: return launch_fm_n<A, 12, TWO>(a, s);
+    case 13: return launch_fm_n<A, 13, TWO>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class A, bool INV>
@@ -316,6 +354,30 @@ hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, con
   if ((e = launch_pm<A, true>(n2, ra, s, rb)) != hipSuccess) return e;
   ca = col_args(p, c, out, out, batch, n1);
   return launch_col<A, true, true>(n1, ca, s);
+}
+
+// Forward transforms of a and b in place and out = a (.) b, with polymul's
+// split (n1 >= 1 or a row part of at most 2^13 words) and row radix.
+template <class A>
+hipError_t fwdmul_cls(const ntt_plan_s* p, int c, void* out, void* a, void* b, uint32_t batch,
+                      uint32_t split, hipStream_t s) {
+  const int n = p->log_n, n1 = (int)split, n2 = n - n1;
+  const int rb = polymul_rb_for(p, split, batch);
+  hipError_t e;
+  if (n2 == 0 || n2 > 13) {
+    // no paired rows for this split: two transforms and the product
+    if ((e = transform_cls<A>(p, c, a, batch, false, split, nullptr, s)) != hipSuccess) return e;
+    if ((e = transform_cls<A>(p, c, b, batch, false, split, nullptr, s)) != hipSuccess) return e;
+    return pointwise_cls<A>(p, c, out, a, b, batch, s);
+  }
+  RowArgs ra = row_args(p, c, a, a, b, batch, n1);
+  ra.dst2 = out;
+  if (n1 == 0) return launch_fm<A, false>(n2, ra, s, rb);
+  ColArgs ca = col_args(p, c, a, a, batch, n1);
+  ca.dst2 = b;
+  ca.src2 = b;
+  if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
+  return launch_fm<A, true>(n2, ra, s, rb);
 }
 
 template <class A>

@@ -170,6 +170,9 @@ template <class A>
 hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                    uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
 template <class A>
+hipError_t fwdmul_cls(const ntt_plan_s* p, int c, void* out, void* a, void* b, uint32_t batch,
+                      uint32_t split, hipStream_t s);
+template <class A>
 hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                      uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s,
                      uint32_t comps, uint32_t levels, uint32_t log_base, const uint32_t* rot);
@@ -186,6 +189,12 @@ hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const
   extern template hipError_t xprod_cls<A>(const ntt_plan_s*, int, void*, const void*,         \
                                           const void*, uint32_t, uint32_t, uint32_t, hipStream_t, \
                                           uint32_t, uint32_t, uint32_t, const uint32_t*);
+#define NTT_EXTERN_FWDMUL(A)                                                             \
+  extern template hipError_t fwdmul_cls<A>(const ntt_plan_s*, int, void*, void*, void*, uint32_t, \
+                                           uint32_t, hipStream_t);
+NTT_EXTERN_FWDMUL(ArF64S)
+NTT_EXTERN_FWDMUL(ArF64L)
+NTT_EXTERN_FWDMUL(ArI64)
 NTT_EXTERN_CLASS(ArF64S)
 NTT_EXTERN_CLASS(ArF64L)
 NTT_EXTERN_CLASS(ArI64)
@@ -638,6 +647,20 @@ ntt_status ntt_cmux(ntt_plan_t plan, void* out, const void* acc, const uint32_t*
   }
   (void)hipFreeAsync(ws, s);
   return st;
+}
+
+ntt_status ntt_forward_mul(ntt_plan_t plan, void* out, void* a, void* b, uint32_t batch,
+                           void* stream) {
+  clear_error();
+  ntt_status st = check_plan_batch(plan, batch);
+  if (st != NTT_OK) return st;
+  if (!out || !a || !b) return fail(NTT_EINVAL, "null data");
+  if (out == a || out == b || a == b) return fail(NTT_EINVAL, "out, a and b must be distinct");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the split of a forward over all 2 * batch polynomials, restricted as polymul's
+  const uint32_t split = polymul_split(plan, call_split(plan, 2 * batch));
+  NTT_FOR_CLASSES(plan, (fwdmul_cls<A>(plan, c, out, a, b, batch, split, s)));
+  return NTT_OK;
 }
 
 ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,
