@@ -544,7 +544,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": "ckks-rns: 4 polys x 36 limbs x N=2^16, 36 largest primes q=1 mod 2^17 "
-                               "below 2^50, u64 words; step = fwd + pointwise (one row pass, ntt_forward_mul) + inv + polymul",
+                               "below 2^50, u64 words; step = fwd + pointwise "
+                               + ("(separate calls)" if args.unfused_step else "(one row pass, ntt_forward_mul)")
+                               + " + inv + polymul",
                    "N": 1 << 16, "limbs": 36, "polys": 4, "word_bits": 64,
                    "transforms_per_step": 504, "parallelism": "single-gpu"},
         "roofline": roofline,
