@@ -410,12 +410,27 @@ hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const v
 
 template <class A, int LOGN2>
 hipError_t launch_xprod_n(const XpArgs& x, uint32_t groups, hipStream_t s) {
-  using S = RowShape<LOGN2, 4>;
-  const uint32_t threads = x.rows * S::TPC;
-  const size_t lds = (size_t)x.rows * ((1u << LOGN2) + (1u << LOGN2) / 16) * sizeof(typename A::V);
+  // Radix-8 slots (twice the threads, half the butterflies per thread) when the
+  // workgroup still fits 1024 threads: the launch is latency-bound, one
+  // workgroup per (group, limb), so a shorter chain per thread is what counts.
+  constexpr uint32_t kN = 1u << LOGN2;
+  const bool r8 = LOGN2 >= 10 && x.rows * (kN / 8) <= 1024;
+  const uint32_t threads = x.rows * (kN >> (r8 ? 3 : 4));
+  const size_t lds = (size_t)x.rows * (kN + kN / 16) * sizeof(typename A::V);
   LaunchTimer t(x.rot ? "cmux" : x.levels ? "xprod_dec" : "xprod", A::kName, LOGN2, false, false,
                 ((uint64_t)groups * x.cols * x.n_cls) << LOGN2, s);
   const dim3 grid(groups * x.n_cls), block(threads);
+  if constexpr (LOGN2 >= 10) {
+    if (r8) {
+      if (x.rot)
+        hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpCmux, 3>), grid, block, lds, s, x);
+      else if (x.levels)
+        hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpDecompose, 3>), grid, block, lds, s, x);
+      else
+        hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpOperands, 3>), grid, block, lds, s, x);
+      return hipGetLastError();
+    }
+  }
   if (x.rot)
     hipLaunchKernelGGL((xprod_kernel<A, LOGN2, kXpCmux>), grid, block, lds, s, x);
   else if (x.levels)

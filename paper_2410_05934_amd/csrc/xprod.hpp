@@ -40,18 +40,18 @@ enum XpMode : int {
   kXpCmux = 2,      // the digits of X^rot acc - acc (acc in `a`); acc is added to the result
 };
 
-// Grid: groups * n_cls workgroups of rows * (N/16) threads; dynamic LDS of
-// rows regions of N + N/16 values (the padded chunk, also for N = 16 where the
-// row pass itself needs no LDS).  Requires cols <= rows.
+// Grid: groups * n_cls workgroups of rows * (N / 2^RB) threads (radix-2^RB
+// rounds); dynamic LDS of rows regions of N + N/16 values (the padded chunk,
+// also for N = 16 where the row pass itself needs no LDS).  Requires
+// cols <= rows.
 // kXpDecompose: the operands are not in memory; slot s = c * levels + j computes
 // digit j of component c of ciphertext `grp` as it loads (Decompose, fused).
 // kXpCmux: one CMux of blind rotation (Sec. II-B, Sec. IV-A): the digits are
 // those of X^r acc - acc (r = rot[grp]), and the stored result is acc plus the
 // inverse transform, i.e. acc + ExtProd(key, X^r acc - acc); cols = comps.
-template <class A, int LOGN2, int MODE = kXpOperands>
+template <class A, int LOGN2, int MODE = kXpOperands, int RB = 4>
 __global__ void __launch_bounds__(1024)
 xprod_kernel(XpArgs args) {
-  constexpr int RB = 4;
   using S = RowShape<LOGN2, RB>;
   using V = typename A::V;
   using W = typename A::W;
