@@ -11,6 +11,10 @@ One step = the whole hot path over one batch:
     inverse NTT of all 4 polynomials            144 limb transforms
     polymul of the 2 pairs (Eq. (1))            144 forward + 72 inverse
 => 504 limb transforms per step; `value` = limb transforms per second.
+The forward and the pointwise products run as one call (ntt_forward_mul: the
+row pass that finishes both transforms of a pair also writes their product);
+--unfused-step times them as two calls, and the other form is always reported
+beside the headline.
 
 Inputs are resident in HBM before timing starts.  The step rotates over
 `--sets` independent copies of its buffers (151 MB each, 1.2 GB for 8) so that
@@ -20,7 +24,9 @@ resident, as they are meant to.
 Also reported: the roofline of the dominant kernel (per-launch HIP events on
 the kernel's own stream, recorded by the library during the timed steps), the
 CPU oracle's throughput on this host, and auxiliary figures (TFHE-shaped batch,
-batched vs one launch per polynomial, single-transform latency).
+external product and CMux step, batched vs one launch per polynomial,
+single-transform latency, ragged batches, serving, automorphism and basis
+conversion).
 """
 from __future__ import annotations
 
