@@ -46,14 +46,32 @@ struct ntt_plan_s {
 
 namespace nttk {
 
-// Column stages used by polymul.  The fused row kernel holds two operands in
-// registers; at 2^14-word rows (1024 threads, at most 128 VGPRs) it would
-// spill, so such plans multiply with a 2^13-word row pass instead.
+// Column stages used by polymul (and forward-and-multiply) for a transform
+// split of n1 column stages.  The fused row kernel holds two operands in
+// registers and is built for rows of at most 2^13 words (at 2^14-word rows,
+// 1024 threads with at most 128 VGPRs, it would spill), so any split whose
+// rows would be longer -- the single pass at N = 2^14, or n1 = log2 N - 14 at
+// N = 2^15 and 2^16 -- takes just enough column stages for 2^13-word rows.
+inline uint32_t polymul_split_log(uint32_t log_n, uint32_t n1) {
+  if (n1 == 0) return log_n <= 13 ? 0u : log_n - 13;
+  return (log_n > 13 && log_n - n1 > 13) ? log_n - 13 : n1;
+}
 inline uint32_t polymul_split(const ntt_plan_s* p, uint32_t n1) {
-  return (n1 == 0 && p->log_n == 14) ? 1u : n1;
+  return polymul_split_log(p->log_n, n1);
 }
 
+// Bounded waits of the single-launch form: polls before a wait gives up, and
+// the testing switch that makes every wait's target unreachable (set through
+// ntt_debug_wait_limit).
+uint32_t fused_spin_limit();
+bool fused_force_expire();
+
 ntt_status fail(ntt_status st, const char* fmt, ...);
+// NTT_FLAG_VALIDATE: check that `polys` polynomials [polys][L][N] at `data` hold
+// canonical words (device-side check; waits for the stream).  NTT_OK when the
+// plan does not have the flag.
+ntt_status validate_words(const ntt_plan_s* p, const void* data, uint64_t polys, hipStream_t s,
+                          const char* name);
 ntt_status hip_fail(hipError_t e, const char* what);
 void clear_error();  // empties the calling thread's last-error message
 

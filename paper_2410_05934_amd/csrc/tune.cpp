@@ -94,7 +94,7 @@ void ensure_env_loaded() {
 
 uint32_t class_of(uint64_t q, uint32_t word_bits) {
   if (word_bits == 32) return 0;
-  return q < ((1ull << 50) - (1ull << 10)) ? 1u : 2u;
+  return q < kF64LBound ? 1u : 2u;
 }
 
 __global__ void fill_words(uint64_t* p, size_t n64) {
@@ -232,8 +232,8 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
   // is a second buffer).  Skipped when that buffer cannot be had.
   uint32_t best_rb_pm = 0;
   if (st == NTT_OK && any) {
-    // polymul's own split rule: a single-pass 2^14 polymul runs two-pass
-    const uint32_t pm_split = (best_split == 0 && log_n == 14) ? 1u : best_split;
+    // polymul's own split rule: its rows are at most 2^13 words
+    const uint32_t pm_split = polymul_split_log((uint32_t)log_n, best_split);
     const int n2 = log_n - (int)pm_split;
     void* out = nullptr;
     if (n2 >= 10 && n2 <= 13 && hipMalloc(&out, bytes) == hipSuccess) {

@@ -156,19 +156,31 @@ def test_pointwise_and_polymul(cls, logn):
 
 
 @pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
-def test_polymul_every_split(cls):
+@pytest.mark.parametrize("logn", [14, 15, 16])
+def test_polymul_every_split(cls, logn):
+    """Every admissible split, including those whose transform rows are 2^14
+    words (single pass at 2^14, n1 = 1 at 2^15, n1 = 2 at 2^16): polymul and
+    forward-and-multiply then take 2^13-word rows, with the same words."""
     word_bits, moduli = CLASSES[cls]
-    N = 1 << 14
+    N = 1 << logn
     a = _data(41, moduli, 1, N, word_bits)
     b = _data(42, moduli, 1, N, word_bits)
     want = oracle.polymul(a, b, moduli)
+    fa, fb = oracle.forward(a, moduli), oracle.forward(b, moduli)
+    want_pw = oracle.pointwise_mul(fa, fb, moduli)
     da, db = to_device(a, word_bits), to_device(b, word_bits)
-    for n1 in _valid_splits(14):
+    for n1 in _valid_splits(logn):
         plan = ntt.Plan(N, moduli, word_bits, flags=ntt.flag_split(n1))
         out = empty_device(a.shape, word_bits)
         plan.polymul(out, da, db)
         torch.cuda.synchronize()
         assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want), n1
+        xa, xb = to_device(a, word_bits), to_device(b, word_bits)
+        plan.forward_mul(out, xa, xb)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out, word_bits).astype(np.uint64), want_pw), n1
+        assert np.array_equal(to_host(xa, word_bits).astype(np.uint64), fa), n1
+        assert np.array_equal(to_host(xb, word_bits).astype(np.uint64), fb), n1
 
 
 def test_c2_full_size():
@@ -228,6 +240,70 @@ def test_c3_tfhe_batch_mac():
     torch.cuda.synchronize()
     assert np.array_equal(to_host(o2, 32).astype(np.uint64),
                           oracle.inverse(want_mac.reshape(G * cols, 1, N), [q]))
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+@pytest.mark.parametrize("logn,groups,rows,cols,tail", [(10, 342, 6, 2, 2), (10, 5, 6, 2, 0),
+                                                        (4, 3, 3, 3, 1), (12, 7, 4, 1, 3)])
+def test_pointwise_mac_groups_and_tail(cls, logn, groups, rows, cols, tail):
+    """ntt_pointwise_mac: groups of `rows` operands with a partial last group of
+    batch_tail (0 = full); the TFHE shape is 342 groups with a tail of 2."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    P = (groups - 1) * rows + (tail or rows)
+    fa = _data(91, moduli, P, N, word_bits)
+    key = _data(92, moduli, rows * cols, N, word_bits)
+    plan = ntt.Plan(N, moduli, word_bits)
+    acc = empty_device((groups * cols, len(moduli), N), word_bits)
+    plan.pointwise_mac(acc, to_device(fa, word_bits), to_device(key, word_bits), rows, cols, groups, tail)
+    torch.cuda.synchronize()
+    want = oracle.mac(fa, key.reshape(rows, cols, len(moduli), N), moduli, rows, cols)
+    assert np.array_equal(to_host(acc, word_bits).astype(np.uint64).reshape(want.shape), want)
+
+
+def test_pointwise_mac_rejects_bad_group_shapes():
+    plan = ntt.Plan(16, Q50[:1], 64)
+    a = empty_device((6, 1, 16), 64)
+    lib = ntt.lib()
+    EINVAL = 1
+    assert lib.ntt_pointwise_mac(plan._h, a.data_ptr(), a.data_ptr(), a.data_ptr(), 3, 1, 0, 0, None) == EINVAL
+    assert lib.ntt_pointwise_mac(plan._h, a.data_ptr(), a.data_ptr(), a.data_ptr(), 3, 1, 2, 4, None) == EINVAL
+    assert lib.ntt_pointwise_mac(plan._h, a.data_ptr(), a.data_ptr(), a.data_ptr(), 0, 1, 2, 0, None) == EINVAL
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
+def test_validate_flag_reports_out_of_range_words(cls):
+    """NTT_FLAG_VALIDATE: canonical inputs give the oracle's words; a word equal
+    to q (or all ones) makes the call return NTT_ERANGE before anything runs,
+    leaving the data untouched, for transforms, polymul, pointwise and MAC."""
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << 12
+    a = _data(95, moduli, 3, N, word_bits)
+    b = _data(96, moduli, 3, N, word_bits)
+    plan = ntt.Plan(N, moduli, word_bits, flags=ntt.FLAG_VALIDATE)
+    assert np.array_equal(_run_fwd(plan, a, word_bits), oracle.forward(a, moduli))
+    out = empty_device(a.shape, word_bits)
+    plan.polymul(out, to_device(a, word_bits), to_device(b, word_bits))
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
+    bad = a.copy()
+    bad[2, len(moduli) - 1, 1234] = moduli[-1]
+    bad[2, len(moduli) - 1, 3000] = (1 << word_bits) - 1
+    d = to_device(bad, word_bits)
+    for call in (lambda: plan.forward(d), lambda: plan.inverse(d),
+                 lambda: plan.polymul(out, to_device(b, word_bits), d),
+                 lambda: plan.pointwise_mul(out, to_device(b, word_bits), d)):
+        with pytest.raises(ntt.NTTError) as e:
+            call()
+        assert e.value.name == "NTT_ERANGE"
+        assert "word 1234 of polynomial 2" in str(e.value)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(d, word_bits).astype(np.uint64), bad)
+    key = to_device(_data(97, moduli, 2, N, word_bits), word_bits)
+    acc = empty_device((2, len(moduli), N), word_bits)
+    with pytest.raises(ntt.NTTError) as e:
+        plan.mac(acc, d, key, 2, 1)
+    assert e.value.name == "NTT_ERANGE"
 
 
 def test_repeat_runs_are_identical():
@@ -415,6 +491,34 @@ def test_single_launch_full_c2_shape_matches_two_launches():
     torch.cuda.synchronize()
     assert torch.equal(d1, d2)
     assert np.array_equal(to_host(d2, 64), a)
+
+
+def test_single_launch_wait_expiry_is_reported():
+    """A wait of the single-launch form that gives up is reported as
+    NTT_ETIMEOUT.  The condition is forced from the host: every wait's target is
+    made unreachable and the poll bound is 4, so each wait gives up quickly and
+    every workgroup still finishes its pieces and exits.  Afterwards the
+    default restores bit-exact results."""
+    mods = Q50[:2]
+    N = 1 << 14
+    a = _data(83, mods, 2, N, 64)
+    plan = ntt.Plan(N, mods, 64, flags=ntt.FLAG_FUSED)
+    d = to_device(a, 64)
+    ntt.debug_wait_limit(4, True)
+    try:
+        with pytest.raises(ntt.NTTError) as e:
+            plan.forward(d)
+        assert e.value.name == "NTT_ETIMEOUT"
+        with pytest.raises(ntt.NTTError) as e:
+            plan.inverse(d)
+        assert e.value.name == "NTT_ETIMEOUT"
+    finally:
+        ntt.debug_wait_limit(0, False)
+    torch.cuda.synchronize()
+    d = to_device(a, 64)
+    plan.forward(d)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(d, 64).astype(np.uint64), oracle.forward(a, mods))
 
 
 @pytest.mark.parametrize("cls", ["u32", "f64", "i64"])
