@@ -40,6 +40,7 @@ double now_s() {
 }
 
 constexpr int kPollUs = 4;       // completion polling interval of the server thread
+constexpr uint64_t kMaxLaunchWords = 1ull << 32;  // words per library call: batch * L * N below this
 constexpr int kMaxCopies = 96;  // descriptors per gather/scatter launch (kernel-argument payload)
 
 struct CopyDesc {
@@ -177,16 +178,36 @@ struct ntt_server_s {
     const bool single = b->reqs.size() == 1 && !host;
     hipError_t e = hipSuccess;
     // Grow this stream's arena to `need` bytes: wait for its earlier batches,
-    // then reallocate (rare: the arena keeps its largest size).
+    // then reallocate (rare: the arena keeps its largest size).  The arenas
+    // together never hold more than the budget: when growing this one would
+    // pass it, the other streams' arenas are released first (after their
+    // streams have finished with them) and regrown on demand.  need is at most
+    // the batch's admitted bytes, which fit in the budget.
     auto reserve = [&](size_t need) -> hipError_t {
-      if (arena_bytes[b->stream] >= need) return hipSuccess;
+      const int me = b->stream;
+      if (arena_bytes[me] >= need) return hipSuccess;
       hipError_t r = hipStreamSynchronize(s);
-      if (r == hipSuccess && arena[b->stream]) r = hipFree(arena[b->stream]);
-      arena[b->stream] = nullptr;
-      arena_bytes[b->stream] = 0;
-      const size_t grow = std::max(need, (size_t)64 << 20);
-      if (r == hipSuccess) r = hipMalloc(&arena[b->stream], grow);
-      if (r == hipSuccess) arena_bytes[b->stream] = grow;
+      if (r == hipSuccess && arena[me]) r = hipFree(arena[me]);
+      arena[me] = nullptr;
+      arena_bytes[me] = 0;
+      const size_t grow = (size_t)std::min<uint64_t>(std::max(need, (size_t)64 << 20),
+                                                     std::max<uint64_t>(need, budget));
+      uint64_t others = 0;
+      for (size_t j = 0; j < arena.size(); ++j) others += arena_bytes[j];
+      for (size_t j = 0; r == hipSuccess && others + grow > budget && j < arena.size(); ++j) {
+        if ((int)j == me || !arena[j]) continue;
+        r = hipStreamSynchronize(streams[j]);
+        if (r == hipSuccess) r = hipFree(arena[j]);
+        others -= arena_bytes[j];
+        arena[j] = nullptr;
+        arena_bytes[j] = 0;
+      }
+      if (r == hipSuccess) r = hipMalloc(&arena[me], grow);
+      if (r == hipSuccess) arena_bytes[me] = grow;
+      uint64_t held = 0;
+      for (size_t j = 0; j < arena.size(); ++j) held += arena_bytes[j];
+      ctr.arena_bytes = held;
+      ctr.max_arena_bytes = std::max(ctr.max_arena_bytes, held);
       return r;
     };
     if (single) {
@@ -310,16 +331,20 @@ struct ntt_server_s {
       b->reqs.push_back(head);
       b->bytes = head->bytes;
       uint32_t polys = head->r.batch;
+      uint64_t words = head->words;
       if (!serial()) {
         const ShapeKey key = shape_of(head);
         for (auto jt = pending.begin(); jt != pending.end();) {
           Req* q = *jt;
           if (b->reqs.size() >= max_reqs) break;
-          if (polys + q->r.batch <= max_batch && inflight_bytes + b->bytes + q->bytes <= budget &&
-              shape_of(q) == key) {
+          // a launch covers fewer than 2^32 words (the library's per-call
+          // limit), so a request never fails because of its batch mates
+          if (polys + q->r.batch <= max_batch && words + q->words < kMaxLaunchWords &&
+              inflight_bytes + b->bytes + q->bytes <= budget && shape_of(q) == key) {
             b->reqs.push_back(q);
             b->bytes += q->bytes;
             polys += q->r.batch;
+            words += q->words;
             jt = pending.erase(jt);
           } else {
             ++jt;
@@ -462,6 +487,11 @@ ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id)
   q->moduli.assign(r->moduli, r->moduli + r->num_moduli);
   q->r.moduli = nullptr;
   q->words = (uint64_t)r->batch * r->num_moduli * r->N;
+  if (q->words >= kMaxLaunchWords) {
+    delete q;
+    return fail(NTT_EINVAL, "request of %llu words: batch * L * N must be below 2^32",
+                (unsigned long long)((uint64_t)r->batch * r->num_moduli * r->N));
+  }
   const uint64_t opnd = q->words * (r->word_bits / 8);
   // Device bytes while in flight: staging for inputs and output (+ the
   // polymul workspace when the transform has a column pass).

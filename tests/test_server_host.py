@@ -128,3 +128,29 @@ def test_replay_submits_at_the_given_times():
     span = t[-1] - t[0]
     assert 0.9 * arrivals[-1] <= span <= arrivals[-1] + 0.05
     assert all(b >= a for a, b in zip(t, t[1:]))
+
+
+def test_a_launch_stays_below_2_to_32_words():
+    """64 forward requests of 64 polynomials x 16 limbs x 2^16 (u32) fit the
+    64 GB budget together but make exactly 2^32 words, the library's per-call
+    limit: the server must split them over launches, so that every request
+    succeeds as it would alone."""
+    mods = synth.primes_below(1 << 32, 1 << 17, 16)
+    words = 64 * 16 * (1 << 16)
+    with ntt.Server(64 << 30, n_streams=1, flags=ntt.SERVER_DRY_RUN) as srv:
+        ids = [srv.submit(ntt.REQ_FORWARD, 1 << 16, mods, 32, 64) for _ in range(64)]
+        infos = [srv.wait(i, 60000) for i in ids]
+    assert all(x["status"] == 0 for x in infos)
+    per_launch = {}
+    for x in infos:
+        per_launch[x["launch_id"]] = per_launch.get(x["launch_id"], 0) + 1
+    assert max(per_launch.values()) * words < (1 << 32)
+    assert max(x["batched_with"] for x in infos) > 1
+
+
+def test_request_of_2_to_32_words_is_rejected_at_submit():
+    mods = synth.primes_below(1 << 32, 1 << 17, 16)
+    with ntt.Server(1 << 40, flags=ntt.SERVER_DRY_RUN) as srv:
+        with pytest.raises(ntt.NTTError) as e:
+            srv.submit(ntt.REQ_FORWARD, 1 << 16, mods, 32, 4096)   # 2^12 x 2^4 x 2^16 words
+        assert e.value.name == "NTT_EINVAL"
