@@ -15,7 +15,10 @@
 // of some transforms run beside the row chunks (VALU bound) of others.
 //
 // The wait is bounded by `spin_limit` polls; by the list order it always ends
-// long before (see fused_order.hpp), so the bound is a safeguard only.
+// long before (see fused_order.hpp), so the bound is a safeguard only.  A wait
+// that gives up raises the launch's `expired` flag, which the host reads back
+// and reports as NTT_ETIMEOUT; the piece then still runs (every address stays
+// inside the transform), so the grid drains normally.
 #pragma once
 
 #include "ntt_kernels.hpp"
@@ -38,7 +41,9 @@ struct FusedArgs {
                               // forward: p1 = N2 / BLOCK column pieces, p2 = N1 row chunks;
                               // inverse: p1 = N1 row chunks, p2 = N2 / BLOCK column pieces
   uint32_t spin_limit;        // polls before a wait gives up
+  uint32_t target_extra;      // added to every wait's target (testing: 1 = unreachable)
   uint32_t* work;             // [0] next item, [1 + t] first-phase pieces done of t
+  uint32_t* expired;          // set to 1 when a wait gave up (zeroed by the host)
 };
 
 // At most 128 VGPRs (four waves per SIMD): the column piece of a 16-word
@@ -79,11 +84,13 @@ fused_kernel(FusedArgs args) {
     const LimbDev& ld = args.limbs[limb];
     if (it.phase == 1) {
       if (threadIdx.x == 0) {
-        uint32_t polls = 0;
-        while (atomicAdd(args.work + 1 + it.t, 0u) < args.p1 && polls < args.spin_limit) {
+        const uint32_t target = args.p1 + args.target_extra;
+        uint32_t polls = 0, seen;
+        while ((seen = atomicAdd(args.work + 1 + it.t, 0u)) < target && polls < args.spin_limit) {
           __builtin_amdgcn_s_sleep(2);
           ++polls;
         }
+        if (seen < target) atomicOr(args.expired, 1u);
       }
       __syncthreads();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

@@ -256,7 +256,7 @@ hipError_t launch_fused(int n1, const FusedArgs& a, int device, hipStream_t s, i
 
 // `work` (nullptr: two launches) holds the counters of the single-launch form
 // for every class of the plan: class c uses 1 + batch * cls_cnt[c] words at
-// offset batch * cls_off[c] + c.
+// offset batch * cls_off[c] + c; the word after all of them is the expiry flag.
 template <class A>
 hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch, bool inv,
                          uint32_t split, uint32_t* work, hipStream_t s) {
@@ -272,8 +272,10 @@ hipError_t transform_cls(const ntt_plan_s* p, int c, void* data, uint32_t batch,
     fa.batch = batch;
     fa.log_n = p->log_n;
     fa.n_tr = batch * p->cls_cnt[c];
-    fa.spin_limit = 1u << 20;
+    fa.spin_limit = fused_spin_limit();
+    fa.target_extra = fused_force_expire() ? 1u : 0u;
     fa.work = work + (size_t)batch * p->cls_off[c] + c;
+    fa.expired = work + (size_t)batch * p->L + 3;
     return inv ? launch_fused<A, true>(n1, fa, p->device, s, rb)
                : launch_fused<A, false>(n1, fa, p->device, s, rb);
   }
