@@ -17,7 +17,7 @@
  * limb l of every polynomial is reduced modulo moduli[l].  Every input must be
  * canonical, in [0, moduli[l]); every output is canonical.  Out-of-range input
  * is a precondition violation: the output is then unspecified, but no call
- * faults on it.
+ * faults on it.  Plans created with NTT_FLAG_VALIDATE check it (NTT_ERANGE).
  *
  * Ownership: the caller owns every data buffer (device memory, e.g. from a
  * PyTorch tensor).  A plan owns its device twiddle tables and is read-only
@@ -49,7 +49,8 @@ typedef enum {
   NTT_EINVAL = 1,     /* bad argument: null pointer, N not a power of two in [2, 2^16], word_bits, ... */
   NTT_ENOTPRIME = 2,  /* a modulus is not prime */
   NTT_ENOROOT = 3,    /* q != 1 (mod 2N): no primitive 2N-th root of unity */
-  NTT_ERANGE = 4,     /* modulus too wide for the word: q >= 2^32 (32-bit) or q >= 2^62 (64-bit) */
+  NTT_ERANGE = 4,     /* modulus too wide for the word: q >= 2^32 (32-bit) or q >= 2^62 (64-bit);
+                         with NTT_FLAG_VALIDATE also an input word outside [0, q) */
   NTT_ENOMEM = 5,     /* device or host allocation failed */
   NTT_EDEVICE = 6,    /* HIP runtime error (no device, launch failure, ...) */
   NTT_EBUSY = 7,      /* resource in use */
@@ -78,11 +79,14 @@ typedef enum {
  * one persistent launch: the one global synchronisation per transform of the
  * paper's single-kernel hybrid NTT (Sec. V-D) becomes a per-transform counter
  * that row (forward) or column (inverse) pieces wait on.  Results are
- * bit-identical to the two-launch form.  The waits are bounded (about 2^20
- * polls); the order of the work list guarantees that they end long before, and
- * the output would be unspecified if one ever expired.  On MI355X this form is
- * slower than the default two launches (cross-XCD release/acquire per piece);
- * it is there for callers that need a single launch per call. */
+ * bit-identical to the two-launch form.  The waits are bounded (2^20 polls by
+ * default, see ntt_debug_wait_limit); the order of the work list guarantees
+ * that they end long before.  A call in this form waits for its stream before
+ * it returns (so it cannot be captured into a graph) and returns NTT_ETIMEOUT
+ * if any wait gave up; its output is then unspecified, but every kernel has
+ * finished normally.  On MI355X this form is slower than the default two
+ * launches (cross-XCD release/acquire per piece); it is there for callers
+ * that need a single launch per call. */
 #define NTT_FLAG_FUSED (1u << 18)
 /* Forward and inverse row passes of 2^8 .. 2^12 words with 4 values per thread
  * (radix-4 rounds: four times the threads of radix-16 rounds and twice the LDS
@@ -91,6 +95,14 @@ typedef enum {
  * regime of the paper's Tab. ntt-mix); polymul rows ignore it.  Exclusive with
  * NTT_FLAG_ROW_RADIX8. */
 #define NTT_FLAG_ROW_RADIX4 (1u << 19)
+/* Check every input word of every call on this plan before its kernels run:
+ * a device-side scan of the inputs (data, a, b, key, ct, acc, in) for words
+ * outside [0, q) of their limb.  Such a call returns NTT_ERANGE, naming the
+ * first offending word (polynomial, limb, index), and launches nothing else,
+ * so its outputs are untouched.  A validated call waits for its stream (the
+ * scan's result is read back), so it cannot be captured into a graph.
+ * Ragged batches and the request server do not validate. */
+#define NTT_FLAG_VALIDATE (1u << 20)
 
 /* Create a plan for length N and num_moduli RNS limbs (Sec. II-D; twiddles are
  * precomputed per modulus as the paper keeps them in constant memory, Sec. II-E).
@@ -142,6 +154,19 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const vo
  * must each hold fewer than 2^32 words (else NTT_EINVAL). */
 ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, uint32_t rows,
                    uint32_t cols, uint32_t num_operands, void* stream);
+
+/* The same grouped multiply-accumulate (Sec. IV-A), sized by groups:
+ *   acc[g][c] = sum over the rows r present in group g of a[g*rows + r] (.) key[r][c]
+ * for g < groups; every group holds `rows` operands except the last, which holds
+ * batch_tail (1 .. rows; 0 means a full last group).  So a holds
+ * (groups - 1) * rows + (batch_tail ? batch_tail : rows) operands [.][L][N],
+ * key [rows][cols][L][N], acc [groups][cols][L][N] (overwritten, not added to;
+ * must not alias a or key).  For the TFHE shape (2048 operands, rows = 6,
+ * cols = 2): groups = 342, batch_tail = 2.  Errors as ntt_mac, plus NTT_EINVAL
+ * for groups or rows 0 or batch_tail > rows. */
+ntt_status ntt_pointwise_mac(ntt_plan_t plan, void* acc, const void* a, const void* key,
+                             uint32_t rows, uint32_t cols, uint32_t groups, uint32_t batch_tail,
+                             void* stream);
 
 /* RNS basis conversion (BConv; Sec. III lists it among the CKKS operators
  * around the NTT).  in[batch][L][N] holds residues of X modulo the source
@@ -267,15 +292,22 @@ ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b,
 
 /* ---- Ragged batches in one persistent launch ---------------------------- */
 
-/* One job of a ragged batch: an in-place forward or inverse transform of
- * data[batch][L][N] under `plan` (any N >= 16, any limb count and moduli). */
+/* One job of a ragged batch under `plan` (any N >= 16, any limb count and
+ * moduli), on [batch][L][N] device words of the plan's width:
+ *   NTT_OP_FORWARD / NTT_OP_INVERSE  transform out in place (a, b NULL or out);
+ *   NTT_OP_POLYMUL                   out = a * b mod (x^N + 1) per limb, as
+ *                                    ntt_polymul (Eq. (1)); a and b are not
+ *                                    modified, out must not overlap them. */
 #define NTT_OP_FORWARD 0u
 #define NTT_OP_INVERSE 1u
+#define NTT_OP_POLYMUL 2u
 typedef struct {
   ntt_plan_t plan;
-  uint32_t op;     /* NTT_OP_FORWARD or NTT_OP_INVERSE */
-  uint32_t batch;  /* polynomials in data */
-  void* data;      /* device words, [batch][L][N] of the plan's width */
+  uint32_t op;     /* NTT_OP_FORWARD, NTT_OP_INVERSE or NTT_OP_POLYMUL */
+  uint32_t batch;  /* polynomials in out (and in a, b) */
+  void* out;       /* device words, [batch][L][N] */
+  const void* a;   /* polymul operands, [batch][L][N] each */
+  const void* b;
 } ntt_job;
 
 typedef struct ntt_ragged_s* ntt_ragged_t;
@@ -286,16 +318,20 @@ typedef struct ntt_ragged_s* ntt_ragged_t;
 #define NTT_RAGGED_ROW_LOG(n2) (((uint32_t)(n2) & 0xfu) << 8) /* with NTT_RAGGED_IN_WORKGROUP: row length 2^n2 (11 or 12) */
 
 /* Build a reusable ragged batch over jobs[0 .. n-1] (the paper's single kernel
- * launch for the hybrid NTT, Sec. V-D, applied to a mixed batch).  Transforms of
- * N <= 2^12 form a work list -- up to 16 limb-rows of one small N per item --
- * built on the host, sorted largest first, uploaded once and run by one
- * persistent launch per word width.  Transforms of N >= 2^13 are grouped by
- * (N, arithmetic class, direction): every limb-row of a group goes into one row
- * table and one column launch plus one row launch cover the group, as the
- * batched transform does for one plan.  With NTT_RAGGED_IN_WORKGROUP they go
- * into the persistent kernel too instead (one workgroup per transform, the
- * intermediate kept with its CU).  The plans and data buffers named by the jobs
- * must stay valid for the life of the handle. */
+ * launch for the hybrid NTT, Sec. V-D, applied to a mixed batch).  Jobs of
+ * N <= 2^12 form a work list -- up to 16 limb-rows of one small N and kind per
+ * item; a product item transforms a and b, multiplies and inverse-transforms
+ * in registers/LDS -- built on the host, sorted largest first, uploaded once
+ * and run by one persistent launch per word width.  Jobs of N >= 2^13 are
+ * grouped by (N, arithmetic class, kind): every limb-row of a group goes into
+ * one row table, and one column launch plus one row launch cover a transform
+ * group (a product group: one column launch over both operands, the fused
+ * product rows, one inverse column launch), as the batched calls do for one
+ * plan.  With NTT_RAGGED_IN_WORKGROUP they go into the persistent kernel too
+ * instead (one workgroup per limb-row, the intermediates kept with its CU).
+ * Products with a column pass use a workspace of batch * L * N words per job,
+ * allocated here and owned by the handle.  The plans and buffers named by the
+ * jobs must stay valid for the life of the handle. */
 ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n, uint32_t flags);
 
 /* Run the batch on `stream`: reset the work counter and launch the persistent
@@ -355,6 +391,8 @@ typedef struct {
   uint64_t max_inflight_requests;
   uint64_t budget_bytes;
   uint64_t plans_cached;
+  uint64_t arena_bytes;         /* staging arenas held now (never above the budget) */
+  uint64_t max_arena_bytes;     /* high-water mark of arena_bytes */
 } ntt_server_counters;
 
 typedef struct ntt_server_s* ntt_server_t;
@@ -372,12 +410,17 @@ typedef struct ntt_server_s* ntt_server_t;
  * tables stay resident for the server's life.  max_batch caps the polynomials
  * per launch (0 = 4096); a launch also takes at most 64 requests.  Batched
  * operands are staged in a per-stream device arena that grows on demand and
- * is reused in stream order. */
+ * is reused in stream order; the arenas together stay within budget_bytes
+ * (another stream's arena is released, after its stream has drained, when
+ * growing one would pass it). */
 ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t n_streams,
                              uint32_t max_batch, uint32_t flags);
 
 /* Queue a request; *id identifies it.  A request larger than the budget is
- * rejected here with NTT_ENOMEM. */
+ * rejected here with NTT_ENOMEM, one of batch * L * N >= 2^32 words with
+ * NTT_EINVAL.  A launch gathers requests of one shape only while their words
+ * stay below 2^32 (the library's per-call limit), so a request that succeeds
+ * alone also succeeds in any mix. */
 ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id);
 
 /* Wait for request `id` (timeout_ms < 0: forever); fills *info and forgets the
@@ -440,6 +483,13 @@ typedef struct {
 ntt_status ntt_stats_enable(int on);
 ntt_status ntt_stats_reset(void);
 ntt_status ntt_stats_collect(ntt_kernel_stat* out, uint32_t cap, uint32_t* count);
+
+/* Testing aid for the bounded waits of persistent launches (NTT_FLAG_FUSED):
+ * polls = polls before a wait gives up (0 restores the default, 2^20);
+ * force_expire != 0 makes every wait's target unreachable, so each wait gives
+ * up after `polls` polls and the call reports NTT_ETIMEOUT while every kernel
+ * still exits normally.  Process-wide; affects calls issued afterwards. */
+ntt_status ntt_debug_wait_limit(uint32_t polls, uint32_t force_expire);
 
 /* Host-only helpers (no device needed). */
 

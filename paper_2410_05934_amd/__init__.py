@@ -16,8 +16,8 @@ import os
 import threading
 
 __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_path",
-           "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_ROW_RADIX4", "FLAG_FUSED", "AUTOMORPH_TRANSFORMED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
-           "RaggedBatch", "batch_ragged", "BasisConversion", "OP_FORWARD", "OP_INVERSE", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
+           "FLAG_FORCE_INT64", "FLAG_ROW_RADIX8", "FLAG_ROW_RADIX4", "FLAG_FUSED", "FLAG_VALIDATE", "AUTOMORPH_TRANSFORMED", "flag_split", "stats_enable", "stats_reset", "stats_collect",
+           "RaggedBatch", "batch_ragged", "debug_wait_limit", "BasisConversion", "OP_FORWARD", "OP_INVERSE", "OP_POLYMUL", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
            "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
            "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
            "SERVER_SERIAL", "SERVER_DRY_RUN"]
@@ -31,6 +31,7 @@ FLAG_FORCE_INT64 = 1 << 16
 FLAG_ROW_RADIX8 = 1 << 17
 FLAG_FUSED = 1 << 18
 FLAG_ROW_RADIX4 = 1 << 19
+FLAG_VALIDATE = 1 << 20
 AUTOMORPH_TRANSFORMED = 1
 BCONV_NO_MFMA = 1
 BCONV_MFMA = 2
@@ -68,6 +69,7 @@ _SIGS = {
     "ntt_inverse": [_vp, _vp, _u32, _vp],
     "ntt_pointwise_mul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_mac": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
+    "ntt_pointwise_mac": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp],
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
@@ -99,6 +101,7 @@ _SIGS = {
     "ntt_server_replay": [_vp, _vp, ctypes.POINTER(ctypes.c_double), _u32, ctypes.POINTER(_u64)],
     "ntt_server_counters_get": [_vp, _vp],
     "ntt_server_destroy": [_vp],
+    "ntt_debug_wait_limit": [_u32, _u32],
     "ntt_stats_enable": [ctypes.c_int],
     "ntt_stats_reset": [],
     "ntt_stats_collect": [_vp, _u32, ctypes.POINTER(_u32)],
@@ -107,6 +110,7 @@ _SIGS = {
 
 OP_FORWARD = 0
 OP_INVERSE = 1
+OP_POLYMUL = 2
 RAGGED_NO_GRAPH = 1
 RAGGED_IN_WORKGROUP = 1 << 1
 
@@ -117,20 +121,36 @@ def ragged_row_log(n2: int) -> int:
 
 
 class _Job(ctypes.Structure):
-    _fields_ = [("plan", _vp), ("op", _u32), ("batch", _u32), ("data", _vp)]
+    _fields_ = [("plan", _vp), ("op", _u32), ("batch", _u32), ("out", _vp), ("a", _vp), ("b", _vp)]
+
+
+def _jobs_array(jobs):
+    """jobs: (plan, OP_FORWARD | OP_INVERSE, tensor) transformed in place, or
+    (plan, OP_POLYMUL, out, a, b)."""
+    arr = (_Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        plan, op = j[0], int(j[1])
+        if op == OP_POLYMUL:
+            out, a, b = j[2], j[3], j[4]
+            n = plan._batch_of(out, f"job {i} out")
+            if plan._batch_of(a, f"job {i} a") != n or plan._batch_of(b, f"job {i} b") != n:
+                raise ValueError(f"job {i}: batch mismatch")
+            arr[i] = _Job(plan._h.value, op, n, out.data_ptr(), a.data_ptr(), b.data_ptr())
+        else:
+            t = j[2]
+            arr[i] = _Job(plan._h.value, op, plan._batch_of(t, f"job {i}"), t.data_ptr(), None, None)
+    return arr
 
 
 class RaggedBatch:
-    """A reusable ragged batch: jobs (plan, op, tensor) run as one persistent
-    launch per word width, replayed from a hipGraph unless no_graph is set.
-    The plans and tensors must outlive the batch."""
+    """A reusable ragged batch: jobs (plan, op, tensor) -- or (plan, OP_POLYMUL,
+    out, a, b) -- run as one persistent launch per word width plus grouped
+    launches, replayed from a hipGraph unless no_graph is set.  The plans and
+    tensors must outlive the batch."""
 
     def __init__(self, jobs, flags: int = 0):
         self._keep = list(jobs)
-        arr = (_Job * len(jobs))()
-        for i, (plan, op, t) in enumerate(jobs):
-            b = plan._batch_of(t, f"job {i}")
-            arr[i] = _Job(plan._h.value, int(op), b, t.data_ptr())
+        arr = _jobs_array(jobs)
         h = _vp()
         _check(lib().ntt_ragged_create(ctypes.byref(h), ctypes.cast(arr, _vp), len(jobs), flags),
                "ntt_ragged_create")
@@ -205,9 +225,7 @@ class BasisConversion:
 
 def batch_ragged(jobs, stream=None) -> None:
     """One-shot ragged batch (no graph); returns after the stream has finished it."""
-    arr = (_Job * len(jobs))()
-    for i, (plan, op, t) in enumerate(jobs):
-        arr[i] = _Job(plan._h.value, int(op), plan._batch_of(t, f"job {i}"), t.data_ptr())
+    arr = _jobs_array(jobs)
     _check(lib().ntt_batch_ragged(ctypes.cast(arr, _vp), len(jobs), _stream_handle(stream)),
            "ntt_batch_ragged")
 
@@ -262,7 +280,8 @@ class _RequestInfo(ctypes.Structure):
 class _ServerCounters(ctypes.Structure):
     _fields_ = [(n, _u64) for n in ("submitted", "completed", "rejected", "launches",
                                     "max_inflight_bytes", "max_inflight_requests",
-                                    "budget_bytes", "plans_cached")]
+                                    "budget_bytes", "plans_cached", "arena_bytes",
+                                    "max_arena_bytes")]
 
 
 class Server:
@@ -335,6 +354,12 @@ class Server:
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_uint64),
                 ("words", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
+
+
+def debug_wait_limit(polls: int = 0, force_expire: bool = False) -> None:
+    """Testing aid: poll bound of the single-launch form's waits (0 = default)
+    and whether every such wait is made to give up (reported as NTT_ETIMEOUT)."""
+    _check(lib().ntt_debug_wait_limit(int(polls), 1 if force_expire else 0), "ntt_debug_wait_limit")
 
 
 def stats_enable(on: bool = True) -> None:
@@ -494,6 +519,23 @@ class Plan:
         _check(lib().ntt_mac(self._h, out.data_ptr(), a.data_ptr(), key.data_ptr(), rows, cols, P,
                              _stream_handle(stream)), "ntt_mac")
         return out
+
+    def pointwise_mac(self, acc, a, key, rows: int, cols: int, groups: int, batch_tail: int = 0,
+                      stream=None):
+        """acc[g][c] = sum_r a[g*rows + r] (.) key[r][c] for g < groups; the last group
+        holds batch_tail operands (0 = rows)."""
+        P = self._batch_of(a, "a")
+        want = (groups - 1) * rows + (batch_tail or rows)
+        if P != want:
+            raise ValueError(f"a holds {P} operands, groups/rows/batch_tail say {want}")
+        if self._batch_of(key, "key") != rows * cols:
+            raise ValueError("key must hold rows*cols polynomials")
+        if self._batch_of(acc, "acc") != groups * cols:
+            raise ValueError("acc must hold groups*cols polynomials")
+        _check(lib().ntt_pointwise_mac(self._h, acc.data_ptr(), a.data_ptr(), key.data_ptr(), rows,
+                                       cols, groups, batch_tail, _stream_handle(stream)),
+               "ntt_pointwise_mac")
+        return acc
 
     def external_product(self, out, a, key, rows: int, cols: int, stream=None):
         """out[g][c] = INTT(sum_r NTT(a[g*rows + r]) (.) key[r][c]); a is not modified."""

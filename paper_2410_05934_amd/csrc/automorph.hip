@@ -134,6 +134,8 @@ ntt_status ntt_automorph(ntt_plan_t plan, void* out, const void* in, uint32_t ba
   a.kinv = kinv & (uint32_t)(two_n - 1);
   a.total = (uint32_t)words;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const ntt_status vst = validate_words(plan, in, batch, s, "in");
+  if (vst != NTT_OK) return vst;
   const bool tr = (flags & NTT_AUTOMORPH_TRANSFORMED) != 0;
   const hipError_t e = plan->word_bits == 32 ? launch_automorph<uint32_t>(a, tr, s)
                                              : launch_automorph<uint64_t>(a, tr, s);

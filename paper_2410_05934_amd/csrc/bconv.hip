@@ -385,7 +385,7 @@ ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_mo
   if (e == hipSuccess) e = hipMemcpy(h->d_c2, c2.data(), c2.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->d_p, dst_moduli, (size_t)M * 8, hipMemcpyHostToDevice);
   // fp64 products when every modulus fits the exact fp64 arithmetic
-  constexpr uint64_t kF64Bound = (1ull << 50) - (1ull << 10);
+  constexpr uint64_t kF64Bound = kF64LBound;
   h->f64 = true;
   for (uint32_t i = 0; i < L; ++i) h->f64 = h->f64 && src_moduli[i] < kF64Bound;
   for (uint32_t j = 0; j < M; ++j) h->f64 = h->f64 && dst_moduli[j] < kF64Bound;

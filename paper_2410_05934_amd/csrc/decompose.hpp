@@ -20,8 +20,8 @@ namespace nttk {
 // [0, B/2] when q <= 2^(levels * log_base - 1).  Both bounds are checked by
 // the caller.
 template <class W>
-__device__ __forceinline__ W signed_digit(W x, uint32_t j, uint32_t levels, uint32_t log_base,
-                                          uint64_t offset, uint64_t q) {
+__host__ __device__ __forceinline__ W signed_digit(W x, uint32_t j, uint32_t levels,
+                                                   uint32_t log_base, uint64_t offset, uint64_t q) {
   const uint64_t y = (uint64_t)x + offset;
   int64_t d;
   if (j + 1 >= levels) {

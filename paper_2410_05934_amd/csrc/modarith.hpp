@@ -71,6 +71,13 @@ NTT_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
 
 constexpr double kTwo52 = 4503599627370496.0;  // 2^52
 
+// Largest modulus (exclusive) of the ArF64L class.  Four inverse (GS) stages
+// double the sum side from centred inputs (|x| <= q/2 + 2) to 8q + 32, which
+// must stay below 2^53; the forward chain (four CT stages from |x| < q, each
+// adding at most q/2 + |x| (q/2) 3 2^-53) stays lower.  2^10 of margin below
+// 2^50 covers the rounding terms.  Larger moduli take the integer class.
+constexpr uint64_t kF64LBound = (1ull << 50) - (1ull << 10);
+
 // x*w - c*q exactly, with c = rint(x * RN(w*qinv)).  |result| <= (1/2 + e)*q
 // where e <= |x*w/q| * 3 * 2^-53 (see the bounds in the design notes).
 NTT_HD double f64_mulmod(double x, double w, double q, double qinv) {

@@ -572,6 +572,66 @@ row_kernel(RowArgs args) {
                                      lds_all + ci * S::CHUNK_LDS, cp.valid);
 }
 
+// Second half of the fused product on one row chunk: the pointwise product of
+// the two forward-transformed register sets, then the inverse rounds, then the
+// store (raw intermediate format with TWO_PASS, canonical words otherwise).
+template <class A, int LOGN2, bool TWO_PASS, int RB>
+__device__ __forceinline__ void product_inverse(const A& ar, typename A::V (&va)[1 << RB],
+                                                const typename A::V (&vb)[1 << RB],
+                                                typename A::W* __restrict__ dst,
+                                                const LimbDev& ld,
+                                                const typename A::TW* __restrict__ twi,
+                                                uint32_t base, uint32_t tt, typename A::V* lds,
+                                                bool valid) {
+  using S = RowShape<LOGN2, RB>;
+  constexpr int R = S::R;
+  constexpr int H0 = S::hb(0);
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    va[u] = ar.mul(va[u], vb[u]);
+    ar.center(va[u]);
+  }
+  row_inverse_from<A, LOGN2, RB, S::K - 1, !TWO_PASS>(ar, va, twi, base, tt, lds, ld);
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      dst[ins_bits<RB>(tt, u, H0)] = TWO_PASS ? ar.to_raw(va[u]) : ar.to_word(va[u]);
+  }
+}
+
+// The whole fused product on one row chunk (the body of polymul_row_kernel for
+// callers that place chunks themselves): sa, sb and dst point at the chunk
+// (dst may equal sa); `base`, `tt`, `lds` and `valid` as for row_chunk.
+template <class A, int LOGN2, bool TWO_PASS, int RB = 4>
+__device__ __forceinline__ void polymul_chunk(typename A::W* __restrict__ dst,
+                                              const typename A::W* sa, const typename A::W* sb,
+                                              const LimbDev& ld, uint32_t base, uint32_t tt,
+                                              typename A::V* lds, bool valid) {
+  using S = RowShape<LOGN2, RB>;
+  constexpr int R = S::R;
+  using V = typename A::V;
+  using W = typename A::W;
+  const A ar(ld);
+  const auto* twf = reinterpret_cast<const typename A::TW*>(ld.twf);
+  const auto* twi = reinterpret_cast<const typename A::TW*>(ld.twi);
+  if constexpr (S::TPC % 64 == 0) {
+    base = __builtin_amdgcn_readfirstlane(base);
+    twf = uniform_ptr(twf);
+    twi = uniform_ptr(twi);
+  }
+  constexpr int H0 = S::hb(0);
+  V va[R], vb[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const W x = sa[ins_bits<RB>(tt, u, H0)];
+    const W y = sb[ins_bits<RB>(tt, u, H0)];
+    va[u] = TWO_PASS ? ar.from_raw(x) : ar.from_word(x);
+    vb[u] = TWO_PASS ? ar.from_raw(y) : ar.from_word(y);
+  }
+  row_forward2_from<A, LOGN2, RB, 0>(ar, va, vb, twf, base, tt, lds);
+  product_inverse<A, LOGN2, TWO_PASS, RB>(ar, va, vb, dst, ld, twi, base, tt, lds, valid);
+}
+
 // Fused negacyclic product on one row chunk: forward(a), forward(b), pointwise
 // product, inverse -- Eq. (1) without leaving registers/LDS.  With TWO_PASS
 // the inputs are column-pass outputs and the result still needs the inverse
@@ -643,17 +703,7 @@ polymul_row_kernel(RowArgs args) {
     put(dp, va);
     return;
   }
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    va[u] = ar.mul(va[u], vb[u]);
-    ar.center(va[u]);
-  }
-  row_inverse_from<A, LOGN2, RB, S::K - 1, !TWO_PASS>(ar, va, twi, cp.base, tt, lds, ld);
-  if (cp.valid) {
-#pragma unroll
-    for (int u = 0; u < R; ++u)
-      dst[ins_bits<RB>(tt, u, H0)] = TWO_PASS ? ar.to_raw(va[u]) : ar.to_word(va[u]);
-  }
+  product_inverse<A, LOGN2, TWO_PASS, RB>(ar, va, vb, dst, ld, twi, cp.base, tt, lds, cp.valid);
 }
 
 // ---------------------------------------------------------------------------

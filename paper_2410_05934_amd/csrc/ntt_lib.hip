@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -64,8 +65,6 @@ static uint64_t root_of(uint32_t N, uint64_t q) {
 
 // ---------------------------------------------------------------------------
 // Plan
-
-static constexpr uint64_t kF64LBound = (1ull << 50) - (1ull << 10);
 
 static uint32_t default_split(int log_n) {
   if (log_n < 4) return (uint32_t)log_n;   // whole transform in the column kernel
@@ -288,15 +287,76 @@ static __global__ void fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Range check of NTT_FLAG_VALIDATE: the smallest flat index of a word that is
+// not below its limb's modulus goes to *first (kept at 0xffffffff otherwise).
+struct CheckArgs {
+  const void* data;      // [polys][L][N]
+  const LimbDev* limbs;  // [L]
+  uint32_t L, log_n;
+  uint32_t total;        // polys * L * N words, < 2^32
+  uint32_t* first;
+};
+
+template <class W>
+static __global__ void __launch_bounds__(256) range_check_kernel(CheckArgs c) {
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= c.total) return;
+  const uint32_t l = (e >> c.log_n) % c.L;
+  if ((uint64_t)static_cast<const W*>(c.data)[e] >= c.limbs[l].q) atomicMin(c.first, e);
+}
+
+// With NTT_FLAG_VALIDATE: check `polys` polynomials of the plan's layout at
+// `data` before anything is launched on them; waits for the stream.  NTT_ERANGE
+// names the first word outside [0, q).
+ntt_status nttk::validate_words(const ntt_plan_s* p, const void* data, uint64_t polys,
+                                hipStream_t s, const char* name) {
+  if (!(p->flags & NTT_FLAG_VALIDATE)) return NTT_OK;
+  const uint64_t total = polys * p->L << p->log_n;
+  if (total >= (1ull << 32)) return fail(NTT_EINVAL, "%s: 2^32 words or more", name);
+  uint32_t* first = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&first), 4, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(range check)");
+  hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, s, first, 1u, 0xffffffffu);
+  CheckArgs c;
+  c.data = data;
+  c.limbs = p->d_limbs;
+  c.L = p->L;
+  c.log_n = p->log_n;
+  c.total = (uint32_t)total;
+  c.first = first;
+  const dim3 grid((uint32_t)((total + 255) / 256));
+  if (p->word_bits == 32) hipLaunchKernelGGL(range_check_kernel<uint32_t>, grid, dim3(256), 0, s, c);
+  else hipLaunchKernelGGL(range_check_kernel<uint64_t>, grid, dim3(256), 0, s, c);
+  e = hipGetLastError();
+  uint32_t bad = 0xffffffffu;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, first, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFreeAsync(first, s);
+  if (e != hipSuccess) return hip_fail(e, "range check");
+  if (bad != 0xffffffffu) {
+    const uint32_t idx = bad & ((1u << p->log_n) - 1u);
+    const uint32_t row = bad >> p->log_n;
+    return fail(NTT_ERANGE, "%s: word %u of polynomial %u, limb %u is not below q = %llu", name,
+                idx, row / p->L, row % p->L, (unsigned long long)p->moduli[row % p->L]);
+  }
+  return NTT_OK;
+}
+
+static std::atomic<uint32_t> g_spin_limit{1u << 20};
+static std::atomic<uint32_t> g_force_expire{0};
+uint32_t nttk::fused_spin_limit() { return g_spin_limit.load(std::memory_order_relaxed); }
+bool nttk::fused_force_expire() { return g_force_expire.load(std::memory_order_relaxed) != 0; }
+
 // Forward or inverse over every class of the plan.  The single-launch form
-// needs 1 + batch * cls_cnt[c] zeroed counters per class (one stream-ordered
-// allocation, cleared by a fill kernel so that the call can be captured).
+// needs 1 + batch * cls_cnt[c] zeroed counters per class and one expiry flag
+// (one stream-ordered allocation, cleared by a fill kernel); it waits for the
+// stream and reads the flag back, so that an expired wait is reported.
 static ntt_status transform_entry(ntt_plan_t plan, void* data, uint32_t batch, bool inv,
                                   hipStream_t s) {
   const uint32_t split = call_split(plan, batch);
   uint32_t* work = nullptr;
+  const uint32_t n = batch * plan->L + 4;
   if (fused_for(plan, inv, split, batch)) {
-    const uint32_t n = batch * plan->L + 3;
     hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&work), (size_t)n * 4, s);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(single-launch counters)");
     hipLaunchKernelGGL(fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, work, n, 0u);
@@ -306,11 +366,20 @@ static ntt_status transform_entry(ntt_plan_t plan, void* data, uint32_t batch, b
       return hip_fail(e, "counter fill");
     }
   }
-  const ntt_status rc = [&]() -> ntt_status {
+  ntt_status rc = [&]() -> ntt_status {
     NTT_FOR_CLASSES(plan, (transform_cls<A>(plan, c, data, batch, inv, split, work, s)));
     return NTT_OK;
   }();
-  if (work) (void)hipFreeAsync(work, s);
+  if (work) {
+    uint32_t expired = 0;
+    hipError_t e = hipMemcpyAsync(&expired, work + (n - 1), 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (rc == NTT_OK && e != hipSuccess) rc = hip_fail(e, "single-launch expiry flag");
+    if (rc == NTT_OK && expired)
+      rc = fail(NTT_ETIMEOUT, "a wait of the single-launch transform gave up after %u polls; "
+                "the output is unspecified", fused_spin_limit());
+    (void)hipFreeAsync(work, s);
+  }
   return rc;
 }
 
@@ -348,6 +417,13 @@ extern "C" {
 const char* ntt_last_error(void) { return g_last_error.c_str(); }
 
 const char* ntt_version(void) { return "mi355x-ntt 0.1 (gfx950)"; }
+
+ntt_status ntt_debug_wait_limit(uint32_t polls, uint32_t force_expire) {
+  clear_error();
+  g_spin_limit.store(polls ? polls : (1u << 20), std::memory_order_relaxed);
+  g_force_expire.store(force_expire ? 1u : 0u, std::memory_order_relaxed);
+  return NTT_OK;
+}
 
 ntt_status ntt_check_modulus(uint32_t N, uint64_t q, uint32_t word_bits) {
   clear_error();
@@ -450,6 +526,8 @@ ntt_status ntt_forward(ntt_plan_t plan, void* data, uint32_t batch, void* stream
   ntt_status st = check_plan_batch(plan, batch);
   if (st != NTT_OK) return st;
   if (!data) return fail(NTT_EINVAL, "null data");
+  st = validate_words(plan, data, batch, static_cast<hipStream_t>(stream), "data");
+  if (st != NTT_OK) return st;
   return transform_entry(plan, data, batch, false, static_cast<hipStream_t>(stream));
 }
 
@@ -458,6 +536,8 @@ ntt_status ntt_inverse(ntt_plan_t plan, void* data, uint32_t batch, void* stream
   ntt_status st = check_plan_batch(plan, batch);
   if (st != NTT_OK) return st;
   if (!data) return fail(NTT_EINVAL, "null data");
+  st = validate_words(plan, data, batch, static_cast<hipStream_t>(stream), "data");
+  if (st != NTT_OK) return st;
   return transform_entry(plan, data, batch, true, static_cast<hipStream_t>(stream));
 }
 
@@ -468,6 +548,8 @@ ntt_status ntt_pointwise_mul(ntt_plan_t plan, void* out, const void* a, const vo
   if (st != NTT_OK) return st;
   if (!out || !a || !b) return fail(NTT_EINVAL, "null data");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = validate_words(plan, a, batch, s, "a")) != NTT_OK) return st;
+  if ((st = validate_words(plan, b, batch, s, "b")) != NTT_OK) return st;
   NTT_FOR_CLASSES(plan, (pointwise_cls<A>(plan, c, out, a, b, batch, s)));
   return NTT_OK;
 }
@@ -486,8 +568,21 @@ ntt_status ntt_mac(ntt_plan_t plan, void* out, const void* a, const void* key, u
       return fail(NTT_EINVAL, "out and key must each hold < 2^32 words");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = validate_words(plan, a, num_operands, s, "a")) != NTT_OK) return st;
+  if ((st = validate_words(plan, key, (uint64_t)rows * cols, s, "key")) != NTT_OK) return st;
   NTT_FOR_CLASSES(plan, (mac_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s)));
   return NTT_OK;
+}
+
+ntt_status ntt_pointwise_mac(ntt_plan_t plan, void* acc, const void* a, const void* key,
+                             uint32_t rows, uint32_t cols, uint32_t groups, uint32_t batch_tail,
+                             void* stream) {
+  clear_error();
+  if (groups == 0 || rows == 0) return fail(NTT_EINVAL, "groups and rows must be >= 1");
+  if (batch_tail > rows) return fail(NTT_EINVAL, "batch_tail=%u exceeds rows=%u", batch_tail, rows);
+  const uint64_t ops = (uint64_t)(groups - 1) * rows + (batch_tail ? batch_tail : rows);
+  if (ops >= (1ull << 32)) return fail(NTT_EINVAL, "too many operands");
+  return ntt_mac(plan, acc, a, key, rows, cols, (uint32_t)ops, stream);
 }
 
 ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const void* key,
@@ -503,6 +598,8 @@ ntt_status ntt_external_product(ntt_plan_t plan, void* out, const void* a, const
   if (groups * cols * poly >= (1ull << 32) || (uint64_t)rows * cols * poly >= (1ull << 32))
     return fail(NTT_EINVAL, "out and key must each hold < 2^32 words");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = validate_words(plan, a, num_operands, s, "a")) != NTT_OK) return st;
+  if ((st = validate_words(plan, key, (uint64_t)rows * cols, s, "key")) != NTT_OK) return st;
   if (xprod_fits(plan, rows, cols, key)) {
     NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, a, key, rows, cols, num_operands, s, 0u, 0u, 0u,
                                         nullptr)));
@@ -549,6 +646,9 @@ ntt_status ntt_external_product_decomposed(ntt_plan_t plan, void* out, const voi
       rows * cols * poly >= (1ull << 32))
     return fail(NTT_EINVAL, "operands, out and key must each hold < 2^32 words");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  ntt_status vst = validate_words(plan, ct, (uint64_t)num_ct * comps, s, "ct");
+  if (vst == NTT_OK) vst = validate_words(plan, key, rows * cols, s, "key");
+  if (vst != NTT_OK) return vst;
   if (xprod_fits(plan, (uint32_t)rows, cols, key)) {
     NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, ct, key, (uint32_t)rows, cols,
                                         (uint32_t)num_operands, s, comps, levels, log_base,
@@ -609,6 +709,9 @@ ntt_status ntt_cmux(ntt_plan_t plan, void* out, const void* acc, const uint32_t*
   if ((uint64_t)num_ct * rows * poly >= (1ull << 32) || rows * comps * poly >= (1ull << 32))
     return fail(NTT_EINVAL, "operands and key must each hold < 2^32 words");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  ntt_status vst = validate_words(plan, acc, (uint64_t)num_ct * comps, s, "acc");
+  if (vst == NTT_OK) vst = validate_words(plan, key, rows * comps, s, "key");
+  if (vst != NTT_OK) return vst;
   if (xprod_fits(plan, (uint32_t)rows, comps, key)) {
     NTT_FOR_CLASSES(plan, (xprod_cls<A>(plan, c, out, acc, key, (uint32_t)rows, comps,
                                         (uint32_t)(num_ct * rows), s, comps, levels, log_base,
@@ -657,6 +760,8 @@ ntt_status ntt_forward_mul(ntt_plan_t plan, void* out, void* a, void* b, uint32_
   if (!out || !a || !b) return fail(NTT_EINVAL, "null data");
   if (out == a || out == b || a == b) return fail(NTT_EINVAL, "out, a and b must be distinct");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = validate_words(plan, a, batch, s, "a")) != NTT_OK) return st;
+  if ((st = validate_words(plan, b, batch, s, "b")) != NTT_OK) return st;
   // the split of a forward over all 2 * batch polynomials, restricted as polymul's
   const uint32_t split = polymul_split(plan, call_split(plan, 2 * batch));
   NTT_FOR_CLASSES(plan, (fwdmul_cls<A>(plan, c, out, a, b, batch, split, s)));
@@ -671,6 +776,8 @@ ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b,
   if (!out || !a || !b) return fail(NTT_EINVAL, "null data");
   if (out == a || out == b) return fail(NTT_EINVAL, "out must not alias a or b");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = validate_words(plan, a, batch, s, "a")) != NTT_OK) return st;
+  if ((st = validate_words(plan, b, batch, s, "b")) != NTT_OK) return st;
   void* ws = nullptr;
   const size_t bytes = polymul_ws_bytes(plan, batch);
   if (bytes) {

@@ -1,9 +1,10 @@
 // ntt_ragged.hip -- ragged batches of transforms in one persistent launch.
 //
-// A ragged batch mixes jobs of different N, limb counts and moduli.  The host
-// turns it into a list of work items -- one limb-row of one job each, or up to
-// 16 limb-rows of the same small N and arithmetic class -- sorted largest
-// first.  One persistent kernel per word width is launched with as many
+// A ragged batch mixes jobs of different N, limb counts and moduli: forward or
+// inverse transforms in place, and negacyclic products out = a * b (Eq. (1)).
+// The host turns it into a list of work items -- one limb-row of one job each,
+// or up to 16 limb-rows of the same small N, arithmetic class and kind --
+// sorted largest first.  One persistent kernel per word width is launched with as many
 // workgroups as fit on the chip at once; each workgroup takes the next item
 // from an atomic counter and transforms its row(s) completely:
 //   N <= 2^12      one row pass in LDS/registers (several rows side by side);
@@ -33,13 +34,19 @@ constexpr int kRaggedBlock = 256;
 constexpr int kRaggedRows = 16;
 constexpr int kRaggedLds = 4096 + 256;  // one 2^12 chunk or several smaller ones, padded
 
+// Job kinds (the op field of ntt_job).
+constexpr uint32_t kOpFwd = NTT_OP_FORWARD, kOpInv = NTT_OP_INVERSE, kOpMul = NTT_OP_POLYMUL;
+
 struct RaggedJobDev {
-  void* data;
+  void* data;        // transforms: the words transformed in place; polymul: the product
+  const void* a;     // polymul operands (natural order, not modified)
+  const void* b;
+  void* ws;          // polymul with a column pass: b's intermediate, [batch][L][N]
   const LimbDev* limbs;
   uint32_t L;
   uint32_t log_n;
   uint32_t log_n2;  // row-pass length inside the workgroup (== log_n for one pass)
-  uint32_t inv;
+  uint32_t op;      // kOpFwd, kOpInv or kOpMul
 };
 
 struct RaggedItem {
@@ -48,7 +55,7 @@ struct RaggedItem {
   uint32_t cls;
   uint32_t log_n;
   uint32_t log_n2;
-  uint32_t inv;
+  uint32_t op;
   uint32_t rows[kRaggedRows];  // flattened row index b * L + l
 };
 
@@ -109,6 +116,102 @@ __device__ __noinline__ void ragged_two_pass(const RaggedJobDev* jp, const Ragge
   __syncthreads();
 }
 
+// Negacyclic products of up to kRaggedRows limb-rows of one small N side by
+// side: each chunk forward-transforms a and b, multiplies and inverse-transforms
+// in registers/LDS (the fused product of polymul), writing out.
+template <class A, int LOGN>
+__device__ __noinline__ void ragged_polymul_single(const RaggedJobDev* jp, const RaggedItem* ip,
+                                                   typename A::V* lds) {
+  using S = RowShape<LOGN>;
+  using W = typename A::W;
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+  const bool valid = ci < ip->nrows;
+  const uint32_t row = ip->rows[valid ? ci : 0];
+  const uint64_t off = (uint64_t)row << LOGN;
+  polymul_chunk<A, LOGN, false>(reinterpret_cast<W*>(jp->data) + off,
+                                reinterpret_cast<const W*>(jp->a) + off,
+                                reinterpret_cast<const W*>(jp->b) + off, jp->limbs[row % jp->L], 1u,
+                                tt, lds + ci * S::CHUNK_LDS, valid);
+}
+
+// One large negacyclic product in one workgroup: the column passes of a (into
+// out) and b (into the job's workspace), the fused product rows over both
+// intermediates, then the inverse column pass of out -- each phase separated by
+// a workgroup barrier, as in ragged_two_pass.
+template <class A, int LOGN1, int LOGN2>
+__device__ __noinline__ void ragged_polymul_two_pass(const RaggedJobDev* jp, const RaggedItem* ip,
+                                                     typename A::V* lds) {
+  using S = RowShape<LOGN2>;
+  using W = typename A::W;
+  const uint32_t N1 = 1u << (jp->log_n - jp->log_n2), N2 = 1u << jp->log_n2;
+  const uint32_t row = ip->rows[0];
+  const uint64_t off = (uint64_t)row << (LOGN1 + LOGN2);
+  W* po = reinterpret_cast<W*>(jp->data) + off;
+  W* pw = reinterpret_cast<W*>(jp->ws) + off;
+  const W* pa = reinterpret_cast<const W*>(jp->a) + off;
+  const W* pb = reinterpret_cast<const W*>(jp->b) + off;
+  const LimbDev& ld = jp->limbs[row % jp->L];
+  const uint32_t ci = threadIdx.x / S::TPC;
+  const uint32_t tt = threadIdx.x & (S::TPC - 1);
+#pragma unroll 1
+  for (uint32_t r = threadIdx.x; r < N2; r += kRaggedBlock) {
+    col_one<A, LOGN1, false, true>(po + r, pa + r, ld, LOGN2, true);
+    col_one<A, LOGN1, false, true>(pw + r, pb + r, ld, LOGN2, true);
+  }
+  __threadfence_block();
+  __syncthreads();
+#pragma unroll 1
+  for (uint32_t c0 = 0; c0 < N1; c0 += kRaggedBlock / S::TPC) {
+    const uint32_t c = c0 + ci;
+    const bool valid = c < N1;
+    const uint64_t co = (uint64_t)(valid ? c : 0) << LOGN2;
+    polymul_chunk<A, LOGN2, true>(po + co, po + co, pw + co, ld, N1 + c, tt,
+                                  lds + ci * S::CHUNK_LDS, valid);
+  }
+  __threadfence_block();
+  __syncthreads();
+#pragma unroll 1
+  for (uint32_t r = threadIdx.x; r < N2; r += kRaggedBlock)
+    col_one<A, LOGN1, true, true>(po + r, po + r, ld, LOGN2, true);
+  __threadfence_block();
+  __syncthreads();
+}
+
+template <class A>
+__device__ void ragged_dispatch_pm(const RaggedJobDev& j, const RaggedItem& it, typename A::V* lds) {
+  if (it.log_n2 == it.log_n) {
+    switch (it.log_n) {
+      case 4: ragged_polymul_single<A, 4>(&j, &it, lds); break;
+      case 5: ragged_polymul_single<A, 5>(&j, &it, lds); break;
+      case 6: ragged_polymul_single<A, 6>(&j, &it, lds); break;
+      case 7: ragged_polymul_single<A, 7>(&j, &it, lds); break;
+      case 8: ragged_polymul_single<A, 8>(&j, &it, lds); break;
+      case 9: ragged_polymul_single<A, 9>(&j, &it, lds); break;
+      case 10: ragged_polymul_single<A, 10>(&j, &it, lds); break;
+      case 11: ragged_polymul_single<A, 11>(&j, &it, lds); break;
+      case 12: ragged_polymul_single<A, 12>(&j, &it, lds); break;
+      default: break;
+    }
+  } else if (it.log_n2 == 12) {
+    switch (it.log_n) {
+      case 13: ragged_polymul_two_pass<A, 1, 12>(&j, &it, lds); break;
+      case 14: ragged_polymul_two_pass<A, 2, 12>(&j, &it, lds); break;
+      case 15: ragged_polymul_two_pass<A, 3, 12>(&j, &it, lds); break;
+      case 16: ragged_polymul_two_pass<A, 4, 12>(&j, &it, lds); break;
+      default: break;
+    }
+  } else if (it.log_n2 == 11) {
+    switch (it.log_n) {
+      case 13: ragged_polymul_two_pass<A, 2, 11>(&j, &it, lds); break;
+      case 14: ragged_polymul_two_pass<A, 3, 11>(&j, &it, lds); break;
+      case 15: ragged_polymul_two_pass<A, 4, 11>(&j, &it, lds); break;
+      case 16: ragged_polymul_two_pass<A, 5, 11>(&j, &it, lds); break;
+      default: break;
+    }
+  }
+}
+
 template <class A, bool INV>
 __device__ void ragged_dispatch_size(const RaggedJobDev& j, const RaggedItem& it,
                                      typename A::V* lds) {
@@ -148,7 +251,8 @@ template <class A>
 __device__ void ragged_dispatch(const RaggedJobDev& j, const RaggedItem& it, double* lds) {
   using V = typename A::V;
   V* l = reinterpret_cast<V*>(lds);
-  if (it.inv) ragged_dispatch_size<A, true>(j, it, l);
+  if (it.op == kOpMul) ragged_dispatch_pm<A>(j, it, l);
+  else if (it.op == kOpInv) ragged_dispatch_size<A, true>(j, it, l);
   else ragged_dispatch_size<A, false>(j, it, l);
 }
 
@@ -190,7 +294,8 @@ __global__ void __launch_bounds__(kRaggedBlock, 4) ragged_kernel(RaggedArgs args
 // batched transform does for one plan.  Table rows are sorted by prime, and
 // row chunks are ordered row-fastest, so neighbouring workgroups share twiddles.
 struct RowRef {
-  void* data;          // 2^log_n words of one limb-row
+  void* data;          // 2^log_n words of one limb-row (written)
+  const void* src;     // the words read by a column pass that is not in place
   const LimbDev* ld;   // its modulus (device copy inside the owning plan)
 };
 
@@ -198,6 +303,7 @@ struct GangArgs {
   const RowRef* rows;
   uint32_t n_rows;
   uint32_t log_n1;     // column stages; rows are 2^12 words
+  uint32_t from_src;   // column pass reads rows[i].src (else rows[i].data, in place)
 };
 
 constexpr int kGangLogN2 = 12;
@@ -209,8 +315,33 @@ __global__ void __launch_bounds__(kColBlock) gang_col_kernel(GangArgs g) {
   const bool valid = gid < (g.n_rows << kGangLogN2);
   const uint32_t x = valid ? gid : 0;
   const RowRef rr = g.rows[x >> kGangLogN2];
-  W* p = reinterpret_cast<W*>(rr.data) + (x & ((1u << kGangLogN2) - 1u));
-  col_one<A, LOGN1, INV, true>(p, p, *rr.ld, kGangLogN2, valid);
+  const uint32_t r = x & ((1u << kGangLogN2) - 1u);
+  W* p = reinterpret_cast<W*>(rr.data) + r;
+  const W* q = g.from_src ? reinterpret_cast<const W*>(rr.src) + r : p;
+  col_one<A, LOGN1, INV, true>(p, q, *rr.ld, kGangLogN2, valid);
+}
+
+// Fused product rows of a polymul group: the table holds n_rows product rows
+// (data = out, intermediate of a) followed by n_rows workspace rows (data =
+// intermediate of b); chunk c of product row i reads both intermediates and
+// writes the product's intermediate over out.
+template <class A>
+__global__ void __launch_bounds__((RowShape<kGangLogN2, 4>::BLOCK), 4) gang_pm_row_kernel(GangArgs g) {
+  using S = RowShape<kGangLogN2, 4>;
+  static_assert(S::CPW == 1, "one chunk per workgroup");
+  using V = typename A::V;
+  using W = typename A::W;
+  __shared__ V lds[S::LDS_ELEMS];
+  const uint32_t total = g.n_rows << g.log_n1;
+  const uint32_t k0 = xcd_block(blockIdx.x, gridDim.x);
+  const bool valid = k0 < total;
+  const uint32_t k = valid ? k0 : 0;
+  const uint32_t i = k % g.n_rows, c = k / g.n_rows;
+  const RowRef ra = g.rows[i], rb = g.rows[i + g.n_rows];
+  W* p = reinterpret_cast<W*>(ra.data) + ((uint64_t)c << kGangLogN2);
+  const W* q = reinterpret_cast<const W*>(rb.data) + ((uint64_t)c << kGangLogN2);
+  polymul_chunk<A, kGangLogN2, true, 4>(p, p, q, *ra.ld, (1u << g.log_n1) + c, threadIdx.x, lds,
+                                        valid);
 }
 
 template <class A, bool INV>
@@ -232,22 +363,47 @@ __global__ void __launch_bounds__((RowShape<kGangLogN2, 4>::BLOCK), 4) gang_row_
 }
 
 template <class A, bool INV>
-hipError_t launch_gang(const GangArgs& g, hipStream_t s, bool timed) {
+hipError_t launch_gang_col(const GangArgs& g, hipStream_t s, bool timed) {
   const uint32_t cols = g.n_rows << kGangLogN2;
+  const uint64_t words = (uint64_t)g.n_rows << (g.log_n1 + kGangLogN2);
+  LaunchTimer t(timed ? "gang_col" : nullptr, A::kName, (int)g.log_n1, INV, true, words, s);
+  const dim3 grid((cols + kColBlock - 1) / kColBlock);
+  switch (g.log_n1) {
+    case 1: hipLaunchKernelGGL((gang_col_kernel<A, 1, INV>), grid, dim3(kColBlock), 0, s, g); break;
+    case 2: hipLaunchKernelGGL((gang_col_kernel<A, 2, INV>), grid, dim3(kColBlock), 0, s, g); break;
+    case 3: hipLaunchKernelGGL((gang_col_kernel<A, 3, INV>), grid, dim3(kColBlock), 0, s, g); break;
+    case 4: hipLaunchKernelGGL((gang_col_kernel<A, 4, INV>), grid, dim3(kColBlock), 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// A polymul group (table: n product rows, then n workspace rows): forward column
+// passes of a and b over all 2n rows in one launch, the fused product rows, the
+// inverse column pass of the product rows.
+template <class A>
+hipError_t launch_gang_pm(GangArgs g, hipStream_t s, bool timed) {
+  GangArgs both = g;
+  both.n_rows = 2 * g.n_rows;
+  both.from_src = 1;
+  hipError_t e = launch_gang_col<A, false>(both, s, timed);
+  if (e != hipSuccess) return e;
+  {
+    const uint64_t words = (uint64_t)g.n_rows << (g.log_n1 + kGangLogN2);
+    LaunchTimer t(timed ? "gang_polymul_row" : nullptr, A::kName, kGangLogN2, false, true, words, s);
+    hipLaunchKernelGGL((gang_pm_row_kernel<A>), dim3(g.n_rows << g.log_n1),
+                       dim3(RowShape<kGangLogN2, 4>::BLOCK), 0, s, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  g.from_src = 0;
+  return launch_gang_col<A, true>(g, s, timed);
+}
+
+template <class A, bool INV>
+hipError_t launch_gang(const GangArgs& g, hipStream_t s, bool timed) {
   const uint32_t chunks = g.n_rows << g.log_n1;
   const uint64_t words = (uint64_t)g.n_rows << (g.log_n1 + kGangLogN2);
-  auto col = [&]() -> hipError_t {
-    LaunchTimer t(timed ? "gang_col" : nullptr, A::kName, (int)g.log_n1, INV, true, words, s);
-    const dim3 grid((cols + kColBlock - 1) / kColBlock);
-    switch (g.log_n1) {
-      case 1: hipLaunchKernelGGL((gang_col_kernel<A, 1, INV>), grid, dim3(kColBlock), 0, s, g); break;
-      case 2: hipLaunchKernelGGL((gang_col_kernel<A, 2, INV>), grid, dim3(kColBlock), 0, s, g); break;
-      case 3: hipLaunchKernelGGL((gang_col_kernel<A, 3, INV>), grid, dim3(kColBlock), 0, s, g); break;
-      case 4: hipLaunchKernelGGL((gang_col_kernel<A, 4, INV>), grid, dim3(kColBlock), 0, s, g); break;
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  };
+  auto col = [&]() -> hipError_t { return launch_gang_col<A, INV>(g, s, timed); };
   auto row = [&]() -> hipError_t {
     LaunchTimer t(timed ? "gang_row" : nullptr, A::kName, kGangLogN2, INV, true, words, s);
     hipLaunchKernelGGL((gang_row_kernel<A, INV>), dim3(chunks),
@@ -279,10 +435,11 @@ struct ntt_ragged_s {
   uint32_t grid[2] = {0, 0};
   // grouped launches of the N >= 2^13 transforms
   struct Gang {
-    uint32_t cls, log_n, inv, off, n;
+    uint32_t cls, log_n, op, off, n;  // polymul: table rows off .. off + 2n - 1
   };
   std::vector<Gang> gangs;
   RowRef* d_rows = nullptr;
+  void* d_ws = nullptr;  // workspace of the polymul jobs with a column pass
   bool use_graph = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -351,9 +508,17 @@ hipError_t launch_all(ntt_ragged_s* r, hipStream_t s, bool timed,
     g.rows = r->d_rows + gg.off;
     g.n_rows = gg.n;
     g.log_n1 = gg.log_n - kGangLogN2;
-    if (gg.cls == 0) e = gg.inv ? launch_gang<ArF64S, true>(g, gs, timed) : launch_gang<ArF64S, false>(g, gs, timed);
-    else if (gg.cls == 1) e = gg.inv ? launch_gang<ArF64L, true>(g, gs, timed) : launch_gang<ArF64L, false>(g, gs, timed);
-    else e = gg.inv ? launch_gang<ArI64, true>(g, gs, timed) : launch_gang<ArI64, false>(g, gs, timed);
+    g.from_src = 0;
+    if (gg.op == kOpMul) {
+      if (gg.cls == 0) e = launch_gang_pm<ArF64S>(g, gs, timed);
+      else if (gg.cls == 1) e = launch_gang_pm<ArF64L>(g, gs, timed);
+      else e = launch_gang_pm<ArI64>(g, gs, timed);
+    } else {
+      const bool inv = gg.op == kOpInv;
+      if (gg.cls == 0) e = inv ? launch_gang<ArF64S, true>(g, gs, timed) : launch_gang<ArF64S, false>(g, gs, timed);
+      else if (gg.cls == 1) e = inv ? launch_gang<ArF64L, true>(g, gs, timed) : launch_gang<ArF64L, false>(g, gs, timed);
+      else e = inv ? launch_gang<ArI64, true>(g, gs, timed) : launch_gang<ArI64, false>(g, gs, timed);
+    }
     if (e != hipSuccess) {
       cleanup();
       return e;
@@ -380,6 +545,7 @@ void free_ragged(ntt_ragged_s* r) {
   if (r->d_items) (void)hipFree(r->d_items);
   if (r->d_counter) (void)hipFree(r->d_counter);
   if (r->d_rows) (void)hipFree(r->d_rows);
+  if (r->d_ws) (void)hipFree(r->d_ws);
   delete r;
 }
 
@@ -400,15 +566,43 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
   }
   std::vector<RaggedItem> wide, narrow;
   const bool in_wg = (flags & NTT_RAGGED_IN_WORKGROUP) != 0;
-  // (class, log_n, inv) -> (twiddle table address, row) for the grouped launches
-  std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<std::pair<uint64_t, RowRef>>> groups;
+  // (class, log_n, op) -> rows for the grouped launches: (twiddle table address,
+  // row, companion row) -- the companion is the workspace row of a polymul
+  struct GroupRow {
+    uint64_t tw;
+    RowRef r, r2;
+  };
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<GroupRow>> groups;
+  // Workspace of the polymul jobs with a column pass (offsets into one
+  // allocation, patched in once it exists): job index -> byte offset.
+  std::vector<std::pair<uint32_t, size_t>> ws_jobs;
+  size_t ws_bytes = 0;
   for (uint32_t ji = 0; ji < n; ++ji) {
     const ntt_job& jb = jobs[ji];
-    if (!jb.plan || !jb.data || jb.batch == 0 || jb.op > 1) {
+    if (!jb.plan || !jb.out || jb.batch == 0 || jb.op > kOpMul) {
       free_ragged(r);
-      return fail(NTT_EINVAL, "job %u: null plan/data, zero batch or bad op", ji);
+      return fail(NTT_EINVAL, "job %u: null plan/out, zero batch or bad op", ji);
     }
     const ntt_plan_s* p = jb.plan;
+    const size_t wbytes = p->word_bits / 8;
+    const uint64_t words = (uint64_t)jb.batch * p->L << p->log_n;
+    if (jb.op == kOpMul) {
+      if (!jb.a || !jb.b) {
+        free_ragged(r);
+        return fail(NTT_EINVAL, "job %u: a polymul job needs a and b", ji);
+      }
+      const uintptr_t o = reinterpret_cast<uintptr_t>(jb.out), bytes = words * wbytes;
+      for (const void* x : {jb.a, jb.b}) {
+        const uintptr_t i = reinterpret_cast<uintptr_t>(x);
+        if (o < i + bytes && i < o + bytes) {
+          free_ragged(r);
+          return fail(NTT_EINVAL, "job %u: out must not overlap a or b", ji);
+        }
+      }
+    } else if ((jb.a && jb.a != jb.out) || (jb.b && jb.b != jb.out)) {
+      free_ragged(r);
+      return fail(NTT_EINVAL, "job %u: a transform job works in place on out (a, b NULL)", ji);
+    }
     if (p->device != r->device) {
       free_ragged(r);
       return fail(NTT_EINVAL, "job %u: plan lives on another device", ji);
@@ -418,23 +612,34 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
       return fail(NTT_EINVAL, "job %u: ragged batches need N >= 16", ji);
     }
     RaggedJobDev jd;
-    jd.data = jb.data;
+    jd.data = jb.out;
+    jd.a = jb.a;
+    jd.b = jb.b;
+    jd.ws = nullptr;
     jd.limbs = p->d_limbs;
     jd.L = p->L;
     jd.log_n = p->log_n;
     jd.log_n2 = ragged_split_for(p->log_n, flags);
-    jd.inv = jb.op;
+    jd.op = jb.op;
+    if (jb.op == kOpMul && p->log_n > 12) {
+      ws_jobs.push_back({ji, ws_bytes});
+      ws_bytes += (size_t)words * wbytes;
+    }
     r->jobs.push_back(jd);
     if (p->log_n > 12 && !in_wg) {
-      const size_t wbytes = p->word_bits / 8;
       for (uint32_t b = 0; b < jb.batch; ++b)
         for (uint32_t l = 0; l < p->L; ++l) {
-          RowRef rr;
-          rr.data = static_cast<unsigned char*>(jb.data) +
-                    (((uint64_t)b * p->L + l) << p->log_n) * wbytes;
-          rr.ld = p->d_limbs + l;
-          groups[std::make_tuple((uint32_t)p->cls[l], p->log_n, jb.op)].push_back(
-              {reinterpret_cast<uint64_t>(p->h_limbs[l].twf), rr});
+          const size_t off = (((uint64_t)b * p->L + l) << p->log_n) * wbytes;
+          GroupRow gr;
+          gr.tw = reinterpret_cast<uint64_t>(p->h_limbs[l].twf);
+          gr.r.data = static_cast<unsigned char*>(jb.out) + off;
+          gr.r.src = jb.op == kOpMul ? static_cast<const unsigned char*>(jb.a) + off : nullptr;
+          gr.r.ld = p->d_limbs + l;
+          // workspace row: an offset for now (patched once the workspace exists)
+          gr.r2.data = reinterpret_cast<void*>(ws_bytes - (size_t)words * wbytes + off);
+          gr.r2.src = jb.op == kOpMul ? static_cast<const unsigned char*>(jb.b) + off : nullptr;
+          gr.r2.ld = gr.r.ld;
+          groups[std::make_tuple((uint32_t)p->cls[l], p->log_n, jb.op)].push_back(gr);
         }
       continue;
     }
@@ -448,7 +653,7 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
       it.cls = c;
       it.log_n = p->log_n;
       it.log_n2 = jd.log_n2;
-      it.inv = jb.op;
+      it.op = jb.op;
       for (uint32_t b = 0; b < jb.batch; ++b) {
         for (uint32_t l = 0; l < p->L; ++l) {
           if (p->cls[l] != c) continue;
@@ -462,29 +667,47 @@ ntt_status ntt_ragged_create(ntt_ragged_t* out, const ntt_job* jobs, uint32_t n,
       if (it.nrows) (c == 0 ? narrow : wide).push_back(it);
     }
   }
-  auto cost = [](const RaggedItem& it) { return (uint64_t)it.nrows * it.log_n << it.log_n; };
+  // a product is three transforms' work
+  auto cost = [](const RaggedItem& it) {
+    return ((uint64_t)it.nrows * it.log_n << it.log_n) * (it.op == kOpMul ? 3u : 1u);
+  };
   auto by_cost = [&](const RaggedItem& a, const RaggedItem& b) { return cost(a) > cost(b); };
   std::stable_sort(narrow.begin(), narrow.end(), by_cost);
   std::stable_sort(wide.begin(), wide.end(), by_cost);
+  if (ws_bytes) {
+    e = hipMalloc(&r->d_ws, ws_bytes);
+    if (e != hipSuccess) {
+      free_ragged(r);
+      return hip_fail(e, "ragged polymul workspace");
+    }
+    for (const auto& jw : ws_jobs)
+      r->jobs[jw.first].ws = static_cast<unsigned char*>(r->d_ws) + jw.second;
+  }
   std::vector<RowRef> table;
   for (auto& kv : groups) {
     auto& v = kv.second;
-    if (((uint64_t)v.size() << std::get<1>(kv.first)) >= (1ull << 32)) {
+    const uint32_t op = std::get<2>(kv.first);
+    if (((uint64_t)v.size() << std::get<1>(kv.first)) * (op == kOpMul ? 2 : 1) >= (1ull << 32)) {
       free_ragged(r);
       return fail(NTT_EINVAL, "a group of 2^%u-word rows holds 2^32 words or more",
                   std::get<1>(kv.first));
     }
-    std::stable_sort(v.begin(), v.end(), [](const std::pair<uint64_t, RowRef>& x,
-                                            const std::pair<uint64_t, RowRef>& y) {
-      return x.first < y.first;
-    });
+    std::stable_sort(v.begin(), v.end(),
+                     [](const GroupRow& x, const GroupRow& y) { return x.tw < y.tw; });
     ntt_ragged_s::Gang gg;
     gg.cls = std::get<0>(kv.first);
     gg.log_n = std::get<1>(kv.first);
-    gg.inv = std::get<2>(kv.first);
+    gg.op = op;
     gg.off = (uint32_t)table.size();
     gg.n = (uint32_t)v.size();
-    for (const auto& x : v) table.push_back(x.second);
+    for (const auto& x : v) table.push_back(x.r);
+    if (op == kOpMul) {
+      for (const auto& x : v) {
+        RowRef w = x.r2;
+        w.data = static_cast<unsigned char*>(r->d_ws) + reinterpret_cast<uintptr_t>(x.r2.data);
+        table.push_back(w);
+      }
+    }
     r->gangs.push_back(gg);
   }
   r->n_items[0] = (uint32_t)narrow.size();
@@ -559,7 +782,7 @@ ntt_status ntt_ragged_run(ntt_ragged_t r, void* stream) {
 ntt_status ntt_ragged_info(ntt_ragged_t r, uint32_t* items, uint32_t* workgroups) {
   if (!r) return fail(NTT_EINVAL, "null ragged batch");
   uint32_t rows = 0;
-  for (const auto& gg : r->gangs) rows += gg.n;
+  for (const auto& gg : r->gangs) rows += gg.n;  // limb-rows (products count once)
   if (items) *items = r->n_items[0] + r->n_items[1] + rows;
   if (workgroups) *workgroups = (r->n_items[0] ? r->grid[0] : 0) + (r->n_items[1] ? r->grid[1] : 0);
   return NTT_OK;
