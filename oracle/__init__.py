@@ -64,6 +64,7 @@ def _load():
                 "orc_polymul": (i32, [_u64p, _u64p, _u64p, u32, u64]),
                 "orc_automorph": (None, [_u64p, _u64p, u32, u64, u64]),
                 "orc_bconv": (None, [_u64p, _u64p, u32, _u64p, u32, _u64p, u32]),
+                "orc_sub_scale": (None, [_u64p, _u64p, _u64p, u32, ctypes.c_uint64, ctypes.c_uint64]),
                 "orc_forward_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
                 "orc_inverse_batch": (i32, [_u64p, u64, u32, u32, _u64p, i32]),
                 "orc_num_cores": (i32, []),
@@ -311,6 +312,44 @@ def bconv(x, src_moduli, dst_moduli) -> np.ndarray:
         lib.orc_bconv(_p(yb), _p(xb), N, _p(src), L, _p(dst), M)
         out[b] = yb
     return out.reshape(a.shape[:-2] + (M, N))
+
+
+def mod_up(x, q_moduli, p_moduli) -> np.ndarray:
+    """ModUp (Sec. III: BConv among the CKKS key-switching operators): the
+    polynomial x[..., L, N] over Q = prod q_i, extended to the basis Q u P:
+    out[..., :L, :] = x and out[..., L:, :] = BConv_{Q->P}(x), i.e. X + alpha Q
+    mod p_j with one 0 <= alpha < L per coefficient (not corrected)."""
+    a = _u64(x)
+    return np.concatenate([a, bconv(a, q_moduli, p_moduli)], axis=-2)
+
+
+def mod_down(x, q_moduli, p_moduli) -> np.ndarray:
+    """ModDown (Sec. III): x[..., L + K, N] over Q u P (the L limbs of Q first,
+    then the K limbs of P) to out[..., L, N] over Q:
+        out_i = (x_i - BConv_{P->Q}(x_P)_i) * P^-1 mod q_i,    P = prod p_k.
+    For X = P Y + e (0 <= e < P) this is Y - alpha mod Q with one
+    0 <= alpha < K per coefficient (the fast conversion's error, not corrected)."""
+    a = _u64(x)
+    qm = [int(q) for q in np.atleast_1d(q_moduli)]
+    pm = [int(p) for p in np.atleast_1d(p_moduli)]
+    L, K, N = len(qm), len(pm), a.shape[-1]
+    assert a.shape[-2] == L + K
+    rows = a.reshape(-1, L + K, N)
+    conv = bconv(rows[:, L:, :], pm, qm)
+    P = 1
+    for pk in pm:
+        P *= pk
+    out = np.empty((rows.shape[0], L, N), dtype=np.uint64)
+    lib = _load()
+    for i, q in enumerate(qm):
+        s = pow(P % q, -1, q)
+        for b in range(rows.shape[0]):
+            xi = np.ascontiguousarray(rows[b, i])
+            ci = np.ascontiguousarray(conv[b, i])
+            yi = np.empty(N, dtype=np.uint64)
+            lib.orc_sub_scale(_p(yi), _p(xi), _p(ci), N, q, s)
+            out[b, i] = yi
+    return out.reshape(a.shape[:-2] + (L, N))
 
 
 # -- one batched CMux step of blind rotation (Sec. II-B, Sec. IV-A) -------------------

@@ -303,6 +303,18 @@ void orc_bconv(uint64_t* y, const uint64_t* x, uint32_t N, const uint64_t* q, ui
   }
 }
 
+/* The last step of ModDown (Sec. III names BConv among the operators of CKKS
+ * key switching; ModDown divides by the special modulus P): for one limb q,
+ * y[n] = (x[n] - c[n]) * s mod q with s = P^-1 mod q and c the BConv of the
+ * P-limbs into q.  Inputs in [0, q). */
+void orc_sub_scale(uint64_t* y, const uint64_t* x, const uint64_t* c, uint32_t N, uint64_t q,
+                   uint64_t s) {
+  for (uint32_t n = 0; n < N; ++n) {
+    const uint64_t d = x[n] >= c[n] ? x[n] - c[n] : x[n] + (q - c[n]);
+    y[n] = mulm(d, s, q);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Batched drivers: data[batch][L][N], moduli[L].  Independent (poly, limb)
  * rows are handed to a pool of threads; each row is transformed by the same

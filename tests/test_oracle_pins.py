@@ -481,6 +481,71 @@ def test_bconv_small_values_are_exact_and_sum_is_explicit():
     assert [[int(v) for v in r] for r in one[0]] == [[int(v) % p for v in x[0, 0]] for p in dst]
 
 
+# -- ModUp / ModDown around BConv (Sec. III) -----------------------------------------
+
+def _residues_of(Z, moduli):
+    return [Z % m for m in moduli]
+
+
+@pytest.mark.parametrize("L,K", [(1, 1), (3, 2), (4, 3), (6, 6)])
+def test_mod_down_divides_by_p_up_to_the_conversion_error(L, K):
+    """For X = P Y + e (0 <= e < P) drawn in big integers over Q u P, ModDown
+    returns Y - alpha mod Q with one integer 0 <= alpha < K per coefficient:
+    checked by CRT of the output over Q.  A wrong sign, a wrong P^-1 or a
+    dropped term fails this."""
+    from paper_2410_05934_amd import synth
+    pool = synth.primes_below(1 << 50, 1 << 17, L + K)
+    qm, pm = pool[:L], pool[L:]
+    Q = P = 1
+    for q in qm:
+        Q *= q
+    for pk in pm:
+        P *= pk
+    rng = random.Random(100 + L * 10 + K)
+    N = 24
+    Zs = [[rng.randrange(Q * P) for _ in range(N)] for _ in range(2)]
+    x = np.array([[[Z % m for Z in row] for m in qm + pm] for row in Zs], dtype=np.uint64)
+    out = oracle.mod_down(x, qm, pm)
+    assert out.shape == (2, L, N)
+    for b in range(2):
+        for n in range(N):
+            Y = Zs[b][n] // P
+            got, _ = _crt([out[b, i, n] for i in range(L)], qm)
+            assert (Y - got) % Q in range(K), (b, n)
+
+
+def test_mod_down_is_exact_on_multiples_of_p():
+    """X = P Y: the P-limbs are zero, so BConv adds nothing and ModDown is Y exactly."""
+    from paper_2410_05934_amd import synth
+    pool = synth.primes_below(1 << 61, 1 << 17, 5)
+    qm, pm = pool[:3], pool[3:]
+    P = pm[0] * pm[1]
+    Q = qm[0] * qm[1] * qm[2]
+    rng = random.Random(7)
+    Ys = [rng.randrange(Q) for _ in range(16)]
+    x = np.array([[[(P * Y) % m for Y in Ys] for m in qm + pm]], dtype=np.uint64)
+    out = oracle.mod_down(x, qm, pm)
+    assert [[int(v) for v in r] for r in out[0]] == [[Y % q for Y in Ys] for q in qm]
+
+
+def test_mod_up_keeps_q_and_extends_by_x_plus_alpha_q():
+    """ModUp keeps the Q-limbs and appends BConv_{Q->P}: each appended residue is
+    X + alpha Q mod p_k with one 0 <= alpha < L shared by all p_k."""
+    from paper_2410_05934_amd import synth
+    pool = synth.primes_below(1 << 50, 1 << 17, 7)
+    qm, pm = pool[:4], pool[4:]
+    x = synth.uniform_poly(77, qm, 2, 16)
+    out = oracle.mod_up(x, qm, pm)
+    assert out.shape == (2, 7, 16)
+    assert np.array_equal(out[:, :4], x)
+    for b in range(2):
+        for n in range(16):
+            X, Q = _crt([x[b, i, n] for i in range(4)], qm)
+            alphas = {al for al in range(4)
+                      if all((X + al * Q - int(out[b, 4 + k, n])) % pm[k] == 0 for k in range(3))}
+            assert len(alphas) == 1, (b, n, alphas)
+
+
 # -- batched CMux ---------------------------------------------------------------------
 
 def test_monomial_mul_matches_schoolbook_with_a_monomial():
