@@ -259,6 +259,31 @@ def run_gpu(args):
                                       "alg_GBps": round(2 * P * L * N * 8 / (t * 1e-3) / 1e9, 1)}
         del yb, conv
         _log(f"[bench] basis conversion 36 -> 36: {extra['c2_bconv_36_to_36']}")
+        # ModUp of the 4 x 36-limb polynomials to Q u P with 36 special primes (the
+        # next 36 primes = 1 mod 2^17 below the CKKS ones), and ModDown back: each
+        # reads 36 (up) or 72 (down) limbs and writes 72 or 36, 108 limb-rows of
+        # 2^16 words per polynomial.  Two wide buffers alternate.
+        ext = ntt.BasisExtension(N, moduli, dst, 64)
+        ups = [empty_device((P, 2 * L, N), 64) for _ in range(2)]
+        dn = empty_device((P, L, N), 64)
+        for j in range(2):
+            ext.mod_up(ups[j], X[j], stream)
+
+        def upcall():
+            j = next(ctr)
+            ext.mod_up(ups[j % 2], X[j % args.sets], stream)
+
+        def downcall():
+            ext.mod_down(dn, ups[next(ctr) % 2], stream)
+        ks_bytes = P * 3 * L * N * 8
+        ks = {}
+        for name, fn in (("mod_up", upcall), ("mod_down", downcall)):
+            t = _time(torch, fn, 2 * args.sets, stream)
+            ks[name] = {"us": round(t * 1e3, 2), "alg_GBps": round(ks_bytes / (t * 1e-3) / 1e9, 1),
+                        "hbm_frac": round(ks_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del ups, dn, ext
+        _log(f"[bench] ModUp / ModDown 36 + 36: {ks}")
+        extra["c2_modup_moddown_36_36"] = ks
         extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
     return value, ms_per_step, roofline, extra
 

@@ -197,6 +197,37 @@ ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_mo
 ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, void* stream);
 ntt_status ntt_bconv_destroy(ntt_bconv_t h);
 
+/* ModUp and ModDown: the basis changes of CKKS key switching built on BConv
+ * (Sec. III lists BConv, ModMul and ModAdd among the operators around the NTT).
+ * A key-switching basis holds L moduli q_i (Q = prod q_i) and K special moduli
+ * p_k (P = prod p_k), all distinct primes.  Polynomials over Q u P are laid out
+ * [batch][L + K][N] with the L limbs of Q first; coefficient domain.
+ *   ntt_mod_up:   in[batch][L][N] over Q -> out[batch][L + K][N]: limbs 0..L-1
+ *                 are in's residues, limb L + k is BConv_{Q->P}(x) mod p_k, i.e.
+ *                 X + alpha Q with one 0 <= alpha < L per coefficient (not
+ *                 corrected).  One launch: the copy is fused into the reads.
+ *   ntt_mod_down: in[batch][L + K][N] over Q u P -> out[batch][L][N] over Q:
+ *                 out_i = (x_i - BConv_{P->Q}(x_P)_i) * (P^-1 mod q_i) mod q_i.
+ *                 For X = P Y + e with 0 <= e < P this is Y - alpha mod Q with one
+ *                 0 <= alpha < K (the fast conversion's error).  One launch: the
+ *                 subtraction and the scale are fused into the conversion's stores.
+ *   create: N a power of two in [2, 65536]; 1 <= L, K <= 64; moduli below 2^32
+ *           (word_bits 32) or 2^62 (word_bits 64); flags as ntt_bconv_create
+ *           (each direction takes the matrix cores under the same rule).
+ *           Constants go to the current device.  Errors: NTT_EINVAL (sizes, flags,
+ *           a modulus in both sets or twice in one), NTT_ENOTPRIME, NTT_ERANGE,
+ *           NTT_ENOMEM / NTT_EDEVICE.
+ *   run:    device pointers; inputs canonical residues; out must not overlap in;
+ *           batch * (L + K) * N below 2^32 words (else NTT_EINVAL).  Asynchronous
+ *           on `stream`; the caller owns both buffers. */
+typedef struct ntt_basis_ext_s* ntt_basis_ext_t;
+ntt_status ntt_basis_ext_create(ntt_basis_ext_t* out, uint32_t N, const uint64_t* q_moduli,
+                                uint32_t L, const uint64_t* p_moduli, uint32_t K,
+                                uint32_t word_bits, uint32_t flags);
+ntt_status ntt_mod_up(ntt_basis_ext_t h, void* out, const void* in, uint32_t batch, void* stream);
+ntt_status ntt_mod_down(ntt_basis_ext_t h, void* out, const void* in, uint32_t batch, void* stream);
+ntt_status ntt_basis_ext_destroy(ntt_basis_ext_t h);
+
 /* Automorphism sigma_k of R_q = Z_q[x]/(x^N+1): b(x) = a(x^k) for odd k,
  * 1 <= k < 2N, on every limb of in[batch][L][N] into out[batch][L][N] (Sec. III
  * names Automorph among the CKKS operators around the NTT; Sec. IV-B builds

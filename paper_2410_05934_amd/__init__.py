@@ -79,6 +79,11 @@ _SIGS = {
                          _u32, _u32, _u32],
     "ntt_bconv": [_vp, _vp, _vp, _u32, _vp],
     "ntt_bconv_destroy": [_vp],
+    "ntt_basis_ext_create": [ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u64), _u32,
+                             ctypes.POINTER(_u64), _u32, _u32, _u32],
+    "ntt_mod_up": [_vp, _vp, _vp, _u32, _vp],
+    "ntt_mod_down": [_vp, _vp, _vp, _u32, _vp],
+    "ntt_basis_ext_destroy": [_vp],
     "ntt_external_product_decomposed": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _u32, _vp],
     "ntt_check_modulus": [_u32, _u64, _u32],
     "ntt_find_root": [_u32, _u64, ctypes.POINTER(_u64)],
@@ -214,6 +219,54 @@ class BasisConversion:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ntt_bconv_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BasisExtension:
+    """The key-switching basis Q = prod q_moduli (L limbs), P = prod p_moduli (K
+    limbs) for length N.  mod_up: x[b][L][N] -> out[b][L + K][N] (x, then
+    BConv_{Q->P}(x)); mod_down: x[b][L + K][N] -> out[b][L][N] with
+    out_i = (x_i - BConv_{P->Q}(x_P)_i) P^-1 mod q_i."""
+
+    def __init__(self, N: int, q_moduli, p_moduli, word_bits: int = 64, mfma=None):
+        self.N, self.word_bits = int(N), int(word_bits)
+        self.L, self.K = len(q_moduli), len(p_moduli)
+        qs = (_u64 * self.L)(*[int(q) for q in q_moduli])
+        ps = (_u64 * self.K)(*[int(p) for p in p_moduli])
+        self._h = _vp()
+        _check(lib().ntt_basis_ext_create(ctypes.byref(self._h), self.N, qs, self.L, ps, self.K,
+                                          self.word_bits,
+                                          0 if mfma is None else (BCONV_MFMA if mfma else BCONV_NO_MFMA)),
+               "ntt_basis_ext_create")
+
+    def _batch(self, t, rows: int, name: str) -> int:
+        return BasisConversion._batch(self, t, rows, name)
+
+    def mod_up(self, out, x, stream=None):
+        b = self._batch(x, self.L, "x")
+        if self._batch(out, self.L + self.K, "out") != b:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_mod_up(self._h, out.data_ptr(), x.data_ptr(), b, _stream_handle(stream)),
+               "ntt_mod_up")
+        return out
+
+    def mod_down(self, out, x, stream=None):
+        b = self._batch(x, self.L + self.K, "x")
+        if self._batch(out, self.L, "out") != b:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_mod_down(self._h, out.data_ptr(), x.data_ptr(), b, _stream_handle(stream)),
+               "ntt_mod_down")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ntt_basis_ext_destroy(self._h)
             self._h = _vp()
 
     def __del__(self):

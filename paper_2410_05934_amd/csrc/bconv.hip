@@ -66,6 +66,16 @@ struct ntt_bconv_s {
   double* d_om = nullptr;    // [M][8][2]: 256^c mod p_j and that over p_j
 };
 
+// The two conversions of key switching between Q = prod q_i and the special
+// modulus P = prod p_k, with the scale of ModDown.
+struct ntt_basis_ext_s {
+  uint32_t N = 0, log_n = 0, L = 0, K = 0, word_bits = 0;
+  ntt_bconv_s* up = nullptr;    // Q -> P
+  ntt_bconv_s* down = nullptr;  // P -> Q
+  uint64_t* d_sc = nullptr;     // [L][2]: s_i = P^-1 mod q_i, floor(s_i 2^64 / q_i)
+  double* d_sf = nullptr;       // [L][2]: s_i, s_i / q_i (fp64 classes)
+};
+
 namespace nttk {
 
 struct BconvArgs {
@@ -80,8 +90,23 @@ struct BconvArgs {
   const uint64_t* kop;
   const double* om;
   uint32_t L, M, log_n;
-  uint32_t total;  // batch * N threads
+  uint32_t total;        // batch * N threads
+  uint64_t in_stride;    // words from one polynomial of `in` to the next
+  uint64_t out_stride;   // words from one polynomial of `out` to the next
+  // ModUp: every source residue the kernel reads is also written to
+  // copy[b * aux_stride + i N + n].  ModDown: output j becomes
+  // (sub[b * aux_stride + j N + n] - y_j) s_j mod p_j.
+  void* copy;
+  const void* sub;
+  uint64_t aux_stride;
+  const uint64_t* sc;    // [M][2]: s_j and floor(s_j 2^64 / p_j)   (ModDown)
+  const double* sf;      // [M][2]: s_j and s_j / p_j               (ModDown)
 };
+
+// What a conversion kernel does around the sum (the template argument MODE).
+constexpr int kBconvPlain = 0;  // y_j
+constexpr int kBconvUp = 1;     // y_j, and the source residues copied beside them
+constexpr int kBconvDown = 2;   // (x_j - y_j) s_j mod p_j
 
 constexpr uint32_t kBconvBlock = 256;
 
@@ -93,15 +118,15 @@ __device__ __forceinline__ uint64_t shoup2(uint64_t y, uint64_t w, uint64_t ws, 
 
 constexpr int kBconvChunk = 8;
 
-template <class W>
+template <class W, int MODE>
 __global__ void __launch_bounds__(kBconvBlock) bconv_kernel(BconvArgs a) {
   constexpr int JB = kBconvChunk;
   const uint32_t gid = blockIdx.x * kBconvBlock + threadIdx.x;
   if (gid >= a.total) return;
   const uint32_t n = gid & ((1u << a.log_n) - 1u);
   const uint32_t b = gid >> a.log_n;
-  const W* x = static_cast<const W*>(a.in) + (((uint64_t)b * a.L) << a.log_n) + n;
-  W* y = static_cast<W*>(a.out) + (((uint64_t)b * a.M) << a.log_n) + n;
+  const W* x = static_cast<const W*>(a.in) + (uint64_t)b * a.in_stride + n;
+  W* y = static_cast<W*>(a.out) + (uint64_t)b * a.out_stride + n;
   for (uint32_t j0 = 0; j0 < a.M; j0 += JB) {
     const uint32_t jn = a.M - j0 < (uint32_t)JB ? a.M - j0 : (uint32_t)JB;
     uint64_t acc[JB];  // each < 2p_j (p < 2^62: acc + product < 4p < 2^64)
@@ -109,7 +134,10 @@ __global__ void __launch_bounds__(kBconvBlock) bconv_kernel(BconvArgs a) {
     for (int jj = 0; jj < JB; ++jj) acc[jj] = 0;
     for (uint32_t i = 0; i < a.L; ++i) {
       const uint64_t q = a.c1[3 * i], w = a.c1[3 * i + 1], ws = a.c1[3 * i + 2];
-      uint64_t t = shoup2((uint64_t)x[(uint64_t)i << a.log_n], w, ws, q);
+      const W xi = x[(uint64_t)i << a.log_n];
+      if (MODE == kBconvUp && j0 == 0)
+        static_cast<W*>(a.copy)[(uint64_t)b * a.aux_stride + ((uint64_t)i << a.log_n) + n] = xi;
+      uint64_t t = shoup2((uint64_t)xi, w, ws, q);
       t = t >= q ? t - q : t;
       const uint64_t* ci = a.c2 + 2 * ((uint64_t)i * a.M + j0);
 #pragma unroll
@@ -124,8 +152,17 @@ __global__ void __launch_bounds__(kBconvBlock) bconv_kernel(BconvArgs a) {
 #pragma unroll
     for (int jj = 0; jj < JB; ++jj) {
       if ((uint32_t)jj < jn) {
-        const uint64_t p = a.p[j0 + jj];
-        y[(uint64_t)(j0 + jj) << a.log_n] = (W)(acc[jj] >= p ? acc[jj] - p : acc[jj]);
+        const uint32_t j = j0 + jj;
+        const uint64_t p = a.p[j];
+        uint64_t r = acc[jj] >= p ? acc[jj] - p : acc[jj];
+        if (MODE == kBconvDown) {
+          const uint64_t xs = static_cast<const W*>(a.sub)[(uint64_t)b * a.aux_stride +
+                                                           ((uint64_t)j << a.log_n) + n];
+          const uint64_t d = xs >= r ? xs - r : xs + (p - r);
+          r = shoup2(d, a.sc[2 * j], a.sc[2 * j + 1], p);
+          r = r >= p ? r - p : r;
+        }
+        y[(uint64_t)j << a.log_n] = (W)r;
       }
     }
   }
@@ -140,15 +177,23 @@ __device__ __forceinline__ double f64_mulmod_pre(double x, double w, double wq, 
   return __builtin_fma(-c, q, h) + l;
 }
 
-template <class W>
+// The ModDown step on a reduced sum r in [0, p): (x - r) s mod p for the
+// residue x in [0, p), with s < p < 2^50 - 2^10 and sq = s / p.  |x - r| < p,
+// so the product is exact as for non-negative operands.
+__device__ __forceinline__ double f64_sub_scale(double x, double r, double s, double sq, double p) {
+  const double v = f64_mulmod_pre(x - r, s, sq, p);
+  return v < 0.0 ? v + p : v;
+}
+
+template <class W, int MODE>
 __global__ void __launch_bounds__(kBconvBlock) bconv_f64_kernel(BconvArgs a) {
   constexpr int JB = kBconvChunk;
   const uint32_t gid = blockIdx.x * kBconvBlock + threadIdx.x;
   if (gid >= a.total) return;
   const uint32_t n = gid & ((1u << a.log_n) - 1u);
   const uint32_t b = gid >> a.log_n;
-  const W* x = static_cast<const W*>(a.in) + (((uint64_t)b * a.L) << a.log_n) + n;
-  W* y = static_cast<W*>(a.out) + (((uint64_t)b * a.M) << a.log_n) + n;
+  const W* x = static_cast<const W*>(a.in) + (uint64_t)b * a.in_stride + n;
+  W* y = static_cast<W*>(a.out) + (uint64_t)b * a.out_stride + n;
   for (uint32_t j0 = 0; j0 < a.M; j0 += JB) {
     const uint32_t jn = a.M - j0 < (uint32_t)JB ? a.M - j0 : (uint32_t)JB;
     double acc[JB];  // |acc| < p/2 + 2 after each centring, < 2^53 between
@@ -156,7 +201,10 @@ __global__ void __launch_bounds__(kBconvBlock) bconv_f64_kernel(BconvArgs a) {
     for (int jj = 0; jj < JB; ++jj) acc[jj] = 0.0;
     for (uint32_t i = 0; i < a.L; ++i) {
       const double* f = a.f1 + 4 * i;
-      double t = f64_mulmod_pre((double)x[(uint64_t)i << a.log_n], f[2], f[3], f[0]);
+      const W xi = x[(uint64_t)i << a.log_n];
+      if (MODE == kBconvUp && j0 == 0)
+        static_cast<W*>(a.copy)[(uint64_t)b * a.aux_stride + ((uint64_t)i << a.log_n) + n] = xi;
+      double t = f64_mulmod_pre((double)xi, f[2], f[3], f[0]);
       t = t < 0.0 ? t + f[0] : t;  // [x_i w_i]_(q_i) in [0, q_i)
       const double* fi = a.f2 + 2 * ((uint64_t)i * a.M + j0);
       const bool recentre = (i & 7u) == 7u;
@@ -173,11 +221,17 @@ __global__ void __launch_bounds__(kBconvBlock) bconv_f64_kernel(BconvArgs a) {
 #pragma unroll
     for (int jj = 0; jj < JB; ++jj) {
       if ((uint32_t)jj < jn) {
-        const double p = a.fp[2 * (j0 + jj)], pinv = a.fp[2 * (j0 + jj) + 1];
+        const uint32_t j = j0 + jj;
+        const double p = a.fp[2 * j], pinv = a.fp[2 * j + 1];
         double r = __builtin_fma(-__builtin_rint(acc[jj] * pinv), p, acc[jj]);
         r = r < 0.0 ? r + p : r;
         r = r >= p ? r - p : r;
-        y[(uint64_t)(j0 + jj) << a.log_n] = (W)(uint64_t)r;
+        if (MODE == kBconvDown) {
+          const W xs = static_cast<const W*>(a.sub)[(uint64_t)b * a.aux_stride +
+                                                    ((uint64_t)j << a.log_n) + n];
+          r = f64_sub_scale((double)xs, r, a.sf[2 * j], a.sf[2 * j + 1], p);
+        }
+        y[(uint64_t)j << a.log_n] = (W)(uint64_t)r;
       }
     }
   }
@@ -189,7 +243,7 @@ constexpr uint64_t kDigitOffset = 0x808080808080ull;  // 128 at digits 0..5
 // One wave per 32 coefficients of one polynomial (N >= 32); four waves per block.
 // SMAX bounds the k-steps (two limbs each) so that the digit words and two sets
 // of constant operands stay in registers.
-template <class W, int SMAX>
+template <class W, int SMAX, int MODE>
 __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t h = lane >> 5;    // which limb of a k-step / which digit half
@@ -200,7 +254,7 @@ __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
   const uint32_t n = (uint32_t)(g & ((1u << a.log_n) - 1u));
   const uint64_t b = g >> a.log_n;
   const uint32_t steps = (a.L + 1u) >> 1;
-  const W* x = static_cast<const W*>(a.in) + ((b * a.L) << a.log_n) + n;
+  const W* x = static_cast<const W*>(a.in) + b * a.in_stride + n;
   // Digits of t_i = [x_i w_i]_(q_i) for the limbs i = 2s + h of this lane.
   uint64_t z[SMAX];
 #pragma unroll
@@ -209,12 +263,15 @@ __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
     const uint32_t i = 2u * st + h;
     if ((uint32_t)st < steps && i < a.L) {
       const double* f = a.f1 + 4 * i;
-      double t = f64_mulmod_pre((double)x[(uint64_t)i << a.log_n], f[2], f[3], f[0]);
+      const W xi = x[(uint64_t)i << a.log_n];
+      if (MODE == kBconvUp)
+        static_cast<W*>(a.copy)[b * a.aux_stride + ((uint64_t)i << a.log_n) + n] = xi;
+      double t = f64_mulmod_pre((double)xi, f[2], f[3], f[0]);
       t = t < 0.0 ? t + f[0] : t;
       z[st] = ((uint64_t)t + kDigitOffset) ^ kDigitOffset;
     }
   }
-  W* y = static_cast<W*>(a.out) + ((b * a.M) << a.log_n) + n;
+  W* y = static_cast<W*>(a.out) + b * a.out_stride + n;
   const uint32_t row_tiles = (a.M + 3u) >> 2;
   const uint64_t* kop = a.kop + lane;
   // Indices are clamped into the table, so no load can leave it whatever the
@@ -264,6 +321,10 @@ __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
         double r = __builtin_fma(-__builtin_rint(sum * pinv), p, sum);
         r = r < 0.0 ? r + p : r;
         r = r >= p ? r - p : r;
+        if (MODE == kBconvDown) {
+          const W xs = static_cast<const W*>(a.sub)[b * a.aux_stride + ((uint64_t)J << a.log_n) + n];
+          r = f64_sub_scale((double)xs, r, a.sf[2 * J], a.sf[2 * J + 1], p);
+        }
         y[(uint64_t)J << a.log_n] = (W)(uint64_t)r;
       }
     }
@@ -273,30 +334,39 @@ __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
   }
 }
 
-template <class W>
-static hipError_t launch_bconv(const BconvArgs& a, bool f64, bool mfma, hipStream_t s) {
+template <class W, int MODE>
+static hipError_t launch_bconv_mode(const BconvArgs& a, bool f64, bool mfma, hipStream_t s) {
+  static const char* const kNames[3][3] = {{"bconv", "bconv_f64", "bconv_mfma"},
+                                           {"modup", "modup_f64", "modup_mfma"},
+                                           {"moddown", "moddown_f64", "moddown_mfma"}};
+  const char* cls = sizeof(W) == 4 ? "u32" : "u64";
   if (mfma) {
     const uint32_t tiles = a.total / 32u;  // N >= 32: tiles never straddle polynomials
-    LaunchTimer t("bconv_mfma", sizeof(W) == 4 ? "u32" : "u64", (int)a.log_n, false, false,
-                  (uint64_t)a.total * a.M, s);
+    LaunchTimer t(kNames[MODE][2], cls, (int)a.log_n, false, false, (uint64_t)a.total * a.M, s);
     const dim3 grid((tiles + 3u) / 4u), block(256);
     const uint32_t steps = (a.L + 1u) / 2u;
-    if (steps <= 8) hipLaunchKernelGGL((bconv_mfma_kernel<W, 8>), grid, block, 0, s, a);
-    else if (steps <= 12) hipLaunchKernelGGL((bconv_mfma_kernel<W, 12>), grid, block, 0, s, a);
-    else if (steps <= 16) hipLaunchKernelGGL((bconv_mfma_kernel<W, 16>), grid, block, 0, s, a);
-    else if (steps <= 20) hipLaunchKernelGGL((bconv_mfma_kernel<W, 20>), grid, block, 0, s, a);
-    else if (steps <= 24) hipLaunchKernelGGL((bconv_mfma_kernel<W, 24>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((bconv_mfma_kernel<W, 32>), grid, block, 0, s, a);
+    if (steps <= 8) hipLaunchKernelGGL((bconv_mfma_kernel<W, 8, MODE>), grid, block, 0, s, a);
+    else if (steps <= 12) hipLaunchKernelGGL((bconv_mfma_kernel<W, 12, MODE>), grid, block, 0, s, a);
+    else if (steps <= 16) hipLaunchKernelGGL((bconv_mfma_kernel<W, 16, MODE>), grid, block, 0, s, a);
+    else if (steps <= 20) hipLaunchKernelGGL((bconv_mfma_kernel<W, 20, MODE>), grid, block, 0, s, a);
+    else if (steps <= 24) hipLaunchKernelGGL((bconv_mfma_kernel<W, 24, MODE>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((bconv_mfma_kernel<W, 32, MODE>), grid, block, 0, s, a);
     return hipGetLastError();
   }
   const uint32_t blocks = (uint32_t)(((uint64_t)a.total + kBconvBlock - 1) / kBconvBlock);
-  LaunchTimer t(f64 ? "bconv_f64" : "bconv", sizeof(W) == 4 ? "u32" : "u64", (int)a.log_n, false,
-                false, (uint64_t)a.total * a.M, s);
+  LaunchTimer t(kNames[MODE][f64 ? 1 : 0], cls, (int)a.log_n, false, false, (uint64_t)a.total * a.M, s);
   if (f64)
-    hipLaunchKernelGGL((bconv_f64_kernel<W>), dim3(blocks), dim3(kBconvBlock), 0, s, a);
+    hipLaunchKernelGGL((bconv_f64_kernel<W, MODE>), dim3(blocks), dim3(kBconvBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((bconv_kernel<W>), dim3(blocks), dim3(kBconvBlock), 0, s, a);
+    hipLaunchKernelGGL((bconv_kernel<W, MODE>), dim3(blocks), dim3(kBconvBlock), 0, s, a);
   return hipGetLastError();
+}
+
+template <class W>
+static hipError_t launch_bconv(const BconvArgs& a, int mode, bool f64, bool mfma, hipStream_t s) {
+  if (mode == kBconvUp) return launch_bconv_mode<W, kBconvUp>(a, f64, mfma, s);
+  if (mode == kBconvDown) return launch_bconv_mode<W, kBconvDown>(a, f64, mfma, s);
+  return launch_bconv_mode<W, kBconvPlain>(a, f64, mfma, s);
 }
 
 static void free_bconv(ntt_bconv_s* h) {
@@ -324,10 +394,11 @@ static uint8_t digit256(uint64_t v, uint32_t c) {
   return (uint8_t)(z >> (8 * c));
 }
 
-ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
-                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits,
-                            uint32_t flags) {
-  clear_error();
+// Checks the arguments of one conversion and puts its constants on the current
+// device; *out owns them (free_bconv).
+static ntt_status bconv_build(ntt_bconv_s** out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
+                              const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits,
+                              uint32_t flags) {
   if (flags & ~(NTT_BCONV_NO_MFMA | NTT_BCONV_MFMA)) return fail(NTT_EINVAL, "unknown flags 0x%x", flags);
   if ((flags & NTT_BCONV_NO_MFMA) && (flags & NTT_BCONV_MFMA))
     return fail(NTT_EINVAL, "NTT_BCONV_NO_MFMA and NTT_BCONV_MFMA are exclusive");
@@ -461,19 +532,12 @@ ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_mo
   return NTT_OK;
 }
 
-ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, void* stream) {
-  clear_error();
-  if (!h) return fail(NTT_EINVAL, "null basis conversion");
-  if (!out || !in) return fail(NTT_EINVAL, "null data");
-  if (batch == 0) return fail(NTT_EINVAL, "batch must be >= 1");
-  const uint64_t in_words = ((uint64_t)batch * h->L) << h->log_n;
-  const uint64_t out_words = ((uint64_t)batch * h->M) << h->log_n;
-  if (in_words >= (1ull << 32) || out_words >= (1ull << 32))
-    return fail(NTT_EINVAL, "batch * L * N and batch * M * N must be < 2^32 words");
-  const uint64_t wb = h->word_bits / 8;
-  const uintptr_t o = reinterpret_cast<uintptr_t>(out), i = reinterpret_cast<uintptr_t>(in);
-  if (o < i + in_words * wb && i < o + out_words * wb)
-    return fail(NTT_EINVAL, "out must not overlap in");
+// One launch of conversion h over `batch` polynomials in the given mode; the
+// caller has checked pointers, sizes and overlaps.
+static ntt_status bconv_run(const ntt_bconv_s* h, int mode, void* out, uint64_t out_stride,
+                            const void* in, uint64_t in_stride, void* copy, const void* sub,
+                            uint64_t aux_stride, const uint64_t* sc, const double* sf,
+                            uint32_t batch, void* stream) {
   BconvArgs a;
   a.out = out;
   a.in = in;
@@ -489,17 +553,168 @@ ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, v
   a.M = h->M;
   a.log_n = h->log_n;
   a.total = (uint32_t)((uint64_t)batch << h->log_n);
+  a.in_stride = in_stride;
+  a.out_stride = out_stride;
+  a.copy = copy;
+  a.sub = sub;
+  a.aux_stride = aux_stride;
+  a.sc = sc;
+  a.sf = sf;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const hipError_t e = h->word_bits == 32 ? launch_bconv<uint32_t>(a, h->f64, h->mfma, s)
-                                          : launch_bconv<uint64_t>(a, h->f64, h->mfma, s);
+  const hipError_t e = h->word_bits == 32 ? launch_bconv<uint32_t>(a, mode, h->f64, h->mfma, s)
+                                          : launch_bconv<uint64_t>(a, mode, h->f64, h->mfma, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return NTT_OK;
+}
+
+static bool overlaps(const void* a, uint64_t a_bytes, const void* b, uint64_t b_bytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + b_bytes && y < x + a_bytes;
+}
+
+ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
+                            const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits,
+                            uint32_t flags) {
+  clear_error();
+  return bconv_build(out, N, src_moduli, L, dst_moduli, M, word_bits, flags);
+}
+
+ntt_status ntt_bconv(ntt_bconv_t h, void* out, const void* in, uint32_t batch, void* stream) {
+  clear_error();
+  if (!h) return fail(NTT_EINVAL, "null basis conversion");
+  if (!out || !in) return fail(NTT_EINVAL, "null data");
+  if (batch == 0) return fail(NTT_EINVAL, "batch must be >= 1");
+  const uint64_t in_words = ((uint64_t)batch * h->L) << h->log_n;
+  const uint64_t out_words = ((uint64_t)batch * h->M) << h->log_n;
+  if (in_words >= (1ull << 32) || out_words >= (1ull << 32))
+    return fail(NTT_EINVAL, "batch * L * N and batch * M * N must be < 2^32 words");
+  const uint64_t wb = h->word_bits / 8;
+  if (overlaps(out, out_words * wb, in, in_words * wb))
+    return fail(NTT_EINVAL, "out must not overlap in");
+  return bconv_run(h, kBconvPlain, out, (uint64_t)h->M << h->log_n, in,
+                   (uint64_t)h->L << h->log_n, nullptr, nullptr, 0, nullptr, nullptr, batch, stream);
 }
 
 ntt_status ntt_bconv_destroy(ntt_bconv_t h) {
   clear_error();
   if (!h) return fail(NTT_EINVAL, "null basis conversion");
   free_bconv(h);
+  return NTT_OK;
+}
+
+static void free_ext(ntt_basis_ext_s* h) {
+  if (!h) return;
+  free_bconv(h->up);
+  free_bconv(h->down);
+  if (h->d_sc) (void)hipFree(h->d_sc);
+  if (h->d_sf) (void)hipFree(h->d_sf);
+  delete h;
+}
+
+ntt_status ntt_basis_ext_create(ntt_basis_ext_t* out, uint32_t N, const uint64_t* q_moduli,
+                                uint32_t L, const uint64_t* p_moduli, uint32_t K,
+                                uint32_t word_bits, uint32_t flags) {
+  clear_error();
+  if (!out || !q_moduli || !p_moduli) return fail(NTT_EINVAL, "null argument");
+  *out = nullptr;
+  if (L == 0 || L > 64 || K == 0 || K > 64)
+    return fail(NTT_EINVAL, "L=%u, K=%u moduli (1 .. 64 each)", L, K);
+  for (uint32_t i = 0; i < L; ++i)
+    for (uint32_t k = 0; k < K; ++k)
+      if (q_moduli[i] == p_moduli[k])
+        return fail(NTT_EINVAL, "q and p moduli must be distinct (%llu in both)",
+                    (unsigned long long)q_moduli[i]);
+  // The first build checks the q_i in full and the p_k only for range; the p_k
+  // are the second build's sources, checked here so that nothing is allocated
+  // for a basis that would fail.
+  if (word_bits != 32 && word_bits != 64) return fail(NTT_EINVAL, "word_bits=%u", word_bits);
+  const uint64_t bound = word_bits == 32 ? (1ull << 32) : (1ull << 62);
+  for (uint32_t k = 0; k < K; ++k) {
+    if (p_moduli[k] >= bound)
+      return fail(NTT_ERANGE, "p=%llu too wide", (unsigned long long)p_moduli[k]);
+    if (!nt_is_prime(p_moduli[k]))
+      return fail(NTT_ENOTPRIME, "p=%llu is not prime", (unsigned long long)p_moduli[k]);
+    for (uint32_t j = 0; j < k; ++j)
+      if (p_moduli[j] == p_moduli[k]) return fail(NTT_EINVAL, "p moduli must be distinct");
+  }
+  ntt_basis_ext_s* h = new (std::nothrow) ntt_basis_ext_s();
+  if (!h) return fail(NTT_ENOMEM, "host allocation");
+  // Each build checks N, word_bits and flags, and that its source moduli are
+  // distinct primes that fit the word: together, that every q_i and p_k is.
+  ntt_status st = bconv_build(&h->up, N, q_moduli, L, p_moduli, K, word_bits, flags);
+  if (st == NTT_OK) st = bconv_build(&h->down, N, p_moduli, K, q_moduli, L, word_bits, flags);
+  if (st != NTT_OK) {
+    free_ext(h);
+    return st;
+  }
+  h->N = N;
+  h->log_n = h->up->log_n;
+  h->L = L;
+  h->K = K;
+  h->word_bits = word_bits;
+  std::vector<uint64_t> sc(2 * (size_t)L);
+  std::vector<double> sf(2 * (size_t)L);
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint64_t q = q_moduli[i];
+    uint64_t pm = 1;  // P mod q_i, nonzero: the moduli are distinct primes
+    for (uint32_t k = 0; k < K; ++k) pm = nt_mul(pm, p_moduli[k] % q, q);
+    const uint64_t s = nt_pow(pm, q - 2, q);
+    sc[2 * i] = s;
+    sc[2 * i + 1] = (uint64_t)(((u128)s << 64) / q);
+    sf[2 * i] = (double)s;
+    sf[2 * i + 1] = (double)s * (1.0 / (double)q);
+  }
+  hipError_t e = hipMalloc(&h->d_sc, sc.size() * 8);
+  if (e == hipSuccess) e = hipMalloc(&h->d_sf, sf.size() * 8);
+  if (e == hipSuccess) e = hipMemcpy(h->d_sc, sc.data(), sc.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_sf, sf.data(), sf.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_ext(h);
+    return hip_fail(e, "key-switching basis constants");
+  }
+  *out = h;
+  return NTT_OK;
+}
+
+// Sizes and overlap of one ModUp / ModDown call: `narrow` has L limbs per
+// polynomial, `wide` L + K.
+static ntt_status ext_check(const ntt_basis_ext_s* h, const void* narrow, const void* wide,
+                            uint32_t batch) {
+  if (!h) return fail(NTT_EINVAL, "null key-switching basis");
+  if (!narrow || !wide) return fail(NTT_EINVAL, "null data");
+  if (batch == 0) return fail(NTT_EINVAL, "batch must be >= 1");
+  const uint64_t wide_words = ((uint64_t)batch * (h->L + h->K)) << h->log_n;
+  if (wide_words >= (1ull << 32)) return fail(NTT_EINVAL, "batch * (L + K) * N must be < 2^32 words");
+  const uint64_t wb = h->word_bits / 8;
+  if (overlaps(narrow, (((uint64_t)batch * h->L) << h->log_n) * wb, wide, wide_words * wb))
+    return fail(NTT_EINVAL, "out must not overlap in");
+  return NTT_OK;
+}
+
+ntt_status ntt_mod_up(ntt_basis_ext_t h, void* out, const void* in, uint32_t batch, void* stream) {
+  clear_error();
+  const ntt_status st = ext_check(h, in, out, batch);
+  if (st != NTT_OK) return st;
+  const uint64_t nq = (uint64_t)h->L << h->log_n, nw = (uint64_t)(h->L + h->K) << h->log_n;
+  char* o = static_cast<char*>(out);
+  return bconv_run(h->up, kBconvUp, o + nq * (h->word_bits / 8), nw, in, nq, out, nullptr, nw,
+                   nullptr, nullptr, batch, stream);
+}
+
+ntt_status ntt_mod_down(ntt_basis_ext_t h, void* out, const void* in, uint32_t batch, void* stream) {
+  clear_error();
+  const ntt_status st = ext_check(h, out, in, batch);
+  if (st != NTT_OK) return st;
+  const uint64_t nq = (uint64_t)h->L << h->log_n, nw = (uint64_t)(h->L + h->K) << h->log_n;
+  const char* x = static_cast<const char*>(in);
+  return bconv_run(h->down, kBconvDown, out, nq, x + nq * (h->word_bits / 8), nw, nullptr, in, nw,
+                   h->d_sc, h->d_sf, batch, stream);
+}
+
+ntt_status ntt_basis_ext_destroy(ntt_basis_ext_t h) {
+  clear_error();
+  if (!h) return fail(NTT_EINVAL, "null key-switching basis");
+  free_ext(h);
   return NTT_OK;
 }
 

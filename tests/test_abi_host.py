@@ -118,3 +118,32 @@ def test_plan_create_rejects_bad_moduli_before_touching_the_device():
     both = ntt.FLAG_ROW_RADIX8 | ntt.FLAG_ROW_RADIX4
     assert lib.ntt_plan_create(ctypes.byref(h), 1024, arr1, 1, 32, both) == 1
     assert b"exclusive" in lib.ntt_last_error()
+
+
+def test_basis_ext_create_rejects_bad_arguments_before_touching_the_device():
+    """ModUp / ModDown basis: sizes, a modulus in both sets, a composite or a too
+    wide modulus are rejected with their codes and no handle."""
+    h = ctypes.c_void_p()
+    lib = ntt.lib()
+    q = (ctypes.c_uint64 * 2)(536881153, 1073707009)
+    p_shared = (ctypes.c_uint64 * 1)(536881153)
+    p_comp = (ctypes.c_uint64 * 1)(536881155)
+    p_wide = (ctypes.c_uint64 * 1)(1 << 62)
+    p_ok = (ctypes.c_uint64 * 2)(1073698817, 1073698817)
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_shared, 1, 64, 0) == 1
+    assert b"distinct" in lib.ntt_last_error()
+    assert h.value is None
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 0, p_comp, 1, 64, 0) == 1
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_comp, 65, 64, 0) == 1
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1000, q, 2, p_ok, 1, 64, 0) == 1
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_comp, 1, 64, 0) == 2
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_wide, 1, 64, 0) == 4
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_ok, 1, 64, 3) == 1
+    assert b"exclusive" in lib.ntt_last_error()
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_ok, 2, 64, 0) == 1
+    assert b"distinct" in lib.ntt_last_error()
+    assert lib.ntt_basis_ext_create(ctypes.byref(h), 1024, q, 2, p_ok, 1, 48, 0) == 1
+    assert h.value is None
+    assert lib.ntt_mod_up(None, None, None, 1, None) == 1
+    assert lib.ntt_mod_down(None, None, None, 1, None) == 1
+    assert lib.ntt_basis_ext_destroy(None) == 1
