@@ -321,6 +321,24 @@ ntt_status ntt_forward_mul(ntt_plan_t plan, void* out, void* a, void* b, uint32_
 ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b, uint32_t batch,
                        void* stream);
 
+/* ntt_polymul for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and words, but the two-pass workspace comes from a
+ * 64 MiB array that the library holds on each GPU it runs on until the process
+ * ends, and the call allocates nothing (no hipMalloc / hipMallocAsync / free).
+ *   - batch * L * N * (word_bits / 8) above 64 MiB for a two-pass product
+ *     (N above the single-pass length) -> NTT_EINVAL; single-pass products
+ *     need no workspace and take any batch ntt_polymul takes.
+ *   - plans created with NTT_FLAG_VALIDATE -> NTT_EINVAL (the range check
+ *     allocates a flag and waits for the stream).
+ *   - every call on one GPU shares that GPU's array: calls that overlap in
+ *     time on one GPU (several streams, unordered host threads) race on it and
+ *     may return wrong words; order them on one stream.
+ *   - the array's device address is looked up on the first call on each
+ *     device (NTT_EDEVICE if that fails). */
+ntt_status ntt_polymul_noalloc(ntt_plan_t plan, void* out, const void* a, const void* b,
+                               uint32_t batch, void* stream);
+
 /* ---- Ragged batches in one persistent launch ---------------------------- */
 
 /* One job of a ragged batch under `plan` (any N >= 16, any limb count and

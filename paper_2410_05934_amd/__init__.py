@@ -72,6 +72,7 @@ _SIGS = {
     "ntt_pointwise_mac": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp],
     "ntt_external_product": [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_polymul": [_vp, _vp, _vp, _vp, _u32, _vp],
+    "ntt_polymul_noalloc": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_automorph": [_vp, _vp, _vp, _u32, _u32, _u32, _vp],
     "ntt_forward_mul": [_vp, _vp, _vp, _vp, _u32, _vp],
     "ntt_cmux": [_vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp],
@@ -667,6 +668,15 @@ class Plan:
             raise ValueError("batch mismatch")
         _check(lib().ntt_polymul(self._h, out.data_ptr(), a.data_ptr(), b.data_ptr(), n,
                                  _stream_handle(stream)), "ntt_polymul")
+        return out
+
+    def polymul_noalloc(self, out, a, b, stream=None):
+        """polymul with the library's fixed per-GPU scratch instead of a pool allocation."""
+        n = self._batch_of(out, "out")
+        if self._batch_of(a, "a") != n or self._batch_of(b, "b") != n:
+            raise ValueError("batch mismatch")
+        _check(lib().ntt_polymul_noalloc(self._h, out.data_ptr(), a.data_ptr(), b.data_ptr(), n,
+                                         _stream_handle(stream)), "ntt_polymul_noalloc")
         return out
 
     def close(self):
