@@ -21,12 +21,23 @@ Inputs are resident in HBM before timing starts.  The step rotates over
 no step finds its data in the 256 MB Infinity Cache.  Twiddle tables stay
 resident, as they are meant to.
 
-Also reported: the roofline of the dominant kernel (per-launch HIP events on
-the kernel's own stream, recorded by the library during the timed steps), the
-CPU oracle's throughput on this host, and auxiliary figures (TFHE-shaped batch,
-external product and CMux step, batched vs one launch per polynomial,
-single-transform latency, ragged batches, serving, automorphism and basis
-conversion).
+`roofline` is the whole forward transform of the 4 x 36 limb-rows (its column
+and row launches, timed per call with HIP events on the library's stream over
+the rotating sets) against 1.25 MiB of algorithmic bytes per limb transform
+(coefficients read and written once, 16 N bytes of twiddles per modulus shared
+by its 4 polynomials); its `valu` entry is the fraction of the chip's VALU issue
+slots the two kernels fill, from their committed rocprofv3 instruction counts
+(profiles/counters.json, used only when taken on the current kernel sources).
+Per-kernel figures (duration, share, algorithmic GB/s, measured HBM bytes, VALU
+issue fraction) are in extra.breakdown and roofline.per_kernel.
+
+Also reported: step-time percentiles, the CPU oracle's throughput on this host
+(all cores and one core), and auxiliary figures (TFHE-shaped batch cold and
+warm, external product and CMux step, batched vs one launch per polynomial,
+single-transform latency, ragged batches, serving, automorphism, basis
+conversion, ModUp and ModDown).
+
+`--summarize-counters` reduces rocprofv3 counter CSVs to profiles/counters.json.
 """
 from __future__ import annotations
 
@@ -85,18 +96,73 @@ def algorithmic_bytes(name: str, words: int, N: int, limbs: int, word_bytes: int
     return 0.0
 
 
-def load_traffic(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
+COUNTERS_PATH = os.path.join(ROOT, "profiles", "counters.json")
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD per
+# 4 cycles (16 lanes), at 2.4 GHz.  The fp64 operations the kernels use (add,
+# mul, fma, rint) all issue at that rate on gfx950 (measured).
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+VALU_CYCLES_PER_INST = 4
+
+
+def load_counters():
+    """Per-kernel figures of the committed rocprofv3 counter runs (HBM bytes and
+    VALU instructions per launch), if they were taken on the current kernel
+    sources; else {}."""
+    if not os.path.exists(COUNTERS_PATH):
+        return {}
+    with open(COUNTERS_PATH) as f:
         rec = json.load(f)
     if rec.get("source_hash") != kernel_source_hash():
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+        return {}
+    return rec.get("kernels", {})
+
+
+def valu_frac(valu_insts: float, seconds: float) -> float:
+    """Fraction of the chip's VALU issue slots that `valu_insts` wave
+    instructions fill in `seconds`."""
+    return valu_insts * VALU_CYCLES_PER_INST / (SIMDS * CLOCK_HZ * seconds)
+
+
+def percentiles(ms_list) -> dict:
+    import numpy as np
+    a = np.asarray(ms_list, dtype=float)
+    return {"median_ms": round(float(np.median(a)), 5), "p10_ms": round(float(np.percentile(a, 10)), 5),
+            "p90_ms": round(float(np.percentile(a, 90)), 5), "mean_ms": round(float(a.mean()), 5),
+            "samples": int(a.size)}
+
+
+def timed_calls(torch, fn, reps, stream):
+    """Per-call durations (ms) from HIP events recorded on `stream` around each call."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        fn(i)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
+def kernel_breakdown(stats: dict, counters: dict, N: int, L: int) -> dict:
+    """Per kernel: launches, mean duration, share of the time, algorithmic GB/s
+    and fraction of HBM peak, and (when the committed counter runs match the
+    sources) measured HBM bytes and the fraction of VALU issue slots used."""
+    total = sum(v["total_ms"] for v in stats.values()) or 1e-9
+    out = {}
+    for name, st in stats.items():
+        sec = st["avg_ms"] * 1e-3
+        b = algorithmic_bytes(name, st["words"] // max(1, st["launches"]), N, L, 8)
+        rec = {"launches": st["launches"], "avg_us": round(st["avg_ms"] * 1e3, 2),
+               "share": round(st["total_ms"] / total, 4),
+               "alg_GBps": round(b / sec / 1e9, 1) if b else None,
+               "hbm_frac": round(b / sec / 1e9 / HBM_PEAK_GBS, 4) if b else None}
+        c = counters.get(name)
+        if c:
+            rec["hbm_bytes_measured"] = c.get("hbm_bytes_per_launch")
+            if c.get("valu_insts_per_launch") is not None:
+                rec["valu_issue_frac"] = round(valu_frac(c["valu_insts_per_launch"], sec), 4)
+        out[name] = rec
+    return out
 
 
 def run_gpu(args):
@@ -112,13 +178,20 @@ def run_gpu(args):
     N, L, P = 1 << 16, 36, 4
     moduli = synth.c2_primes(L)
     tuned = {}
-    if not args.no_tune:
+    if args.tune_file and os.path.exists(args.tune_file):
+        # the choices of an earlier tuned run (so that a profiled run launches
+        # the same kernels as the timed one)
+        ntt.tune_load(args.tune_file)
+        tuned["loaded"] = args.tune_file
+    elif not args.no_tune:
         # The autotuner picks the pass split for this shape (and for the pairs
         # inside polymul) before anything is timed.
         for batch in (P, P // 2):
             n1, us = ntt.tune_split(N, moduli, 64, batch)
             tuned[f"split_b{batch}"] = {"n1": n1, "fwd_inv_us": round(us, 2)}
         _log(f"[bench] tuned: {tuned}")
+        if args.tune_file:
+            ntt.tune_save(args.tune_file)
     plan = ntt.Plan(N, moduli, 64, flags=ntt.FLAG_ROW_RADIX8 if args.row_radix8 else 0)
     _log(f"[bench] plan N={N} L={L} split n1={plan.split}; generating inputs")
     host = synth.uniform_poly(args.seed, moduli, P, N)
@@ -165,10 +238,15 @@ def run_gpu(args):
     value = transforms_per_step * args.steps / (ms / 1e3)
     _log(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.4g} limb-NTT/s (wall {wall:.3f}s)")
 
+    # The same K steps with an event between consecutive steps: the spread of
+    # the step time (median, p10, p90).
+    step_ms = timed_calls(torch, lambda i: step(i), args.steps, stream)
+
     # The same K steps again with the library's per-launch events (two HIP
     # events on the kernel's own stream around every launch): per-kernel
-    # durations for the breakdown and the roofline.  The events add a little
-    # time between launches, so `value` comes from the run above.
+    # durations for the breakdown.  The events add a little time between
+    # launches, so `value` comes from the run above.
+    counters = load_counters()
     ntt.stats_reset()
     ntt.stats_enable(True)
     t0.record(stream)
@@ -180,23 +258,7 @@ def run_gpu(args):
     stats = ntt.stats_collect()
     ms_events = t0.elapsed_time(t1) / args.steps
     _log(f"[bench] with per-launch events: {ms_events:.4f} ms/step")
-
-    # Dominant kernel and its roofline.
-    breakdown = {}
-    for name, s in stats.items():
-        b = algorithmic_bytes(name, s["words"] // max(1, s["launches"]), N, L, 8)
-        breakdown[name] = {"launches": s["launches"], "avg_us": round(s["avg_ms"] * 1e3, 2),
-                           "share": round(s["total_ms"] / max(1e-9, sum(v["total_ms"] for v in stats.values())), 4),
-                           "alg_GBps": round(b / (s["avg_ms"] * 1e-3) / 1e9, 1) if b else None}
-    dom = max(stats, key=lambda k: stats[k]["total_ms"])
-    d = stats[dom]
-    alg = algorithmic_bytes(dom, d["words"] // d["launches"], N, L, 8)
-    achieved = alg / (d["avg_ms"] * 1e-3) / 1e9
-    traffic = load_traffic(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "alg_bytes_per_launch": alg,
-                "avg_launch_us": round(d["avg_ms"] * 1e3, 2)}
+    breakdown = kernel_breakdown(stats, counters, N, L)
 
     # The same steps with the forward and the pointwise product as two calls.
     t0.record(stream)
@@ -205,27 +267,66 @@ def run_gpu(args):
     t1.record(stream)
     torch.cuda.synchronize()
     ms_other = t0.elapsed_time(t1) / args.steps
+
+    import itertools
+    rot = itertools.count()
+    # Roofline: the whole forward transform of the 4 x 36 limb-rows (column pass
+    # and row pass, two launches) over the rotating sets, one HIP event pair per
+    # call on the library's stream.  Algorithmic bytes per limb transform:
+    # 2 N W (every coefficient read and written once) + the twiddles, 16 N bytes
+    # per modulus per launch shared by the 4 polynomials of that modulus: 1.25 MiB
+    # at N = 2^16, W = 8 B; 144 limb transforms per call.
+    reps = 4 * args.sets
+    fwd_mean = _time(torch, lambda: plan.forward(X[next(rot) % args.sets], stream), reps, stream)
+    inv_mean = _time(torch, lambda: plan.inverse(X[next(rot) % args.sets], stream), reps, stream)
+    fwd_ms = timed_calls(torch, lambda i: plan.forward(X[i % args.sets], stream), reps, stream)
+    inv_ms = timed_calls(torch, lambda i: plan.inverse(X[i % args.sets], stream), reps, stream)
+    ntt.stats_reset()
+    ntt.stats_enable(True)
+    for i in range(reps):
+        plan.forward(X[i % args.sets], stream)
+    torch.cuda.synchronize()
+    ntt.stats_enable(False)
+    fstats = ntt.stats_collect()
+    fwd_kernels = {k: v for k, v in kernel_breakdown(fstats, counters, N, L).items()}
+    limb_ntt_bytes = 2 * N * 8 + 16 * N // P  # 1.25 MiB
+    alg = 144 * limb_ntt_bytes
+    t_fwd = percentiles(fwd_ms)
+    t_avg_s = fwd_mean * 1e-3
+    achieved = alg / t_avg_s / 1e9
+    hbm = [counters.get(k, {}).get("hbm_bytes_per_launch") for k in fwd_kernels]
+    traffic = sum(hbm) if hbm and all(h is not None for h in hbm) else None
+    vi = [counters.get(k, {}).get("valu_insts_per_launch") for k in fwd_kernels]
+    valu = None
+    if vi and all(v is not None for v in vi):
+        valu = {"insts_per_launch": sum(vi), "issue_frac": round(valu_frac(sum(vi), t_avg_s), 4),
+                "peak": "1024 SIMDs x one wave64 VALU instruction per 4 cycles at 2.4 GHz"}
+    roofline = {"bound": "hbm", "kernel": "forward transform, 4 x 36 x 2^16: " + " + ".join(sorted(fwd_kernels)),
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": alg, "avg_launch_us": round(fwd_mean * 1e3, 2),
+                "time_percentiles_ms_event_per_call": t_fwd, "valu": valu, "per_kernel": fwd_kernels}
+    _log(f"[bench] forward transform: {fwd_mean * 1e3:.2f} us, {achieved:.1f} GB/s = "
+         f"{achieved / HBM_PEAK_GBS:.4f} of HBM peak; kernels {fwd_kernels}")
     extra = {"breakdown": breakdown, "ms_per_step_with_launch_events": round(ms_events, 4),
+             "step_time_percentiles": percentiles(step_ms),
              ("ms_per_step_fused_forward_mul" if args.unfused_step else "ms_per_step_unfused"):
                  round(ms_other, 4),
              "rotating_sets": args.sets, "split_used": plan.split_for(P), "tuned": tuned}
+    coeff_bytes = 144 * 2 * N * 8
+    whole = {}
+    for name, ms_list, t in (("forward", fwd_ms, fwd_mean), ("inverse", inv_ms, inv_mean)):
+        pc = percentiles(ms_list)
+        whole[name] = {"us": round(t * 1e3, 2), "limb_ntt_per_s": 144 / (t * 1e-3),
+                       "rns_poly_ntt_per_s": 4 / (t * 1e-3),
+                       "hbm_frac_coefficients": round(coeff_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "hbm_frac_with_tables": round(alg / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "percentiles_ms": pc}
+    _log(f"[bench] whole transforms: {whole}")
+    extra["c2_whole_transform"] = whole
     if not args.no_aux:
-        # Whole transforms (forward alone, inverse alone) over the rotating sets:
-        # algorithmic bytes per C2 forward = every coefficient read and written
-        # once (144 x 1 MiB) plus one fp64 table of N entries per modulus (36 x 0.5 MiB).
         import itertools
         ctr = itertools.count()
-        t_fwd = _time(torch, lambda: plan.forward(X[next(ctr) % args.sets], stream), 4 * args.sets, stream)
-        t_inv = _time(torch, lambda: plan.inverse(X[next(ctr) % args.sets], stream), 4 * args.sets, stream)
-        coeff_bytes = 144 * 2 * N * 8
-        table_bytes = L * N * 8
-        whole = {}
-        for name, t in (("forward", t_fwd), ("inverse", t_inv)):
-            whole[name] = {"us": round(t * 1e3, 2), "limb_ntt_per_s": 144 / (t * 1e-3),
-                           "hbm_frac_coefficients": round(coeff_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "hbm_frac_with_tables": round((coeff_bytes + table_bytes) / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        _log(f"[bench] whole transforms: {whole}")
-        extra["c2_whole_transform"] = whole
         # Automorphism sigma_5 of every limb (coefficient domain, then the forward
         # transform's slot order) from the rotating sets into two output buffers:
         # algorithmic bytes = every word read once and written once.
@@ -284,7 +385,7 @@ def run_gpu(args):
         del ups, dn, ext
         _log(f"[bench] ModUp / ModDown 36 + 36: {ks}")
         extra["c2_modup_moddown_36_36"] = ks
-        extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X[0], stream))
+        extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X, stream))
     return value, ms_per_step, roofline, extra
 
 
@@ -301,13 +402,32 @@ def _time(torch, fn, reps, stream):
     return a.elapsed_time(b) / reps
 
 
-def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, stream):
+def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, X, stream):
     out = {}
-    # C2 batched (one call over 4 polynomials) vs plain (one call per RNS polynomial).
+    # C2 batched (one call over 4 polynomials) vs plain (one call per RNS
+    # polynomial): cold over the rotating sets, and warm on one set (75.5 MB,
+    # resident in the 256 MB Infinity Cache after the first call).
+    import itertools
+    ctr = itertools.count()
+    x2 = X[0]
+
+    def cold_batched():
+        plan2.forward(X[next(ctr) % args.sets], stream)
+
+    def cold_plain():
+        x = X[next(ctr) % args.sets]
+        for i in range(4):
+            plan2.forward(x[i:i + 1], stream)
+    t_bc = _time(torch, cold_batched, 4 * args.sets, stream)
+    t_pc = _time(torch, cold_plain, 4 * args.sets, stream)
     t_b = _time(torch, lambda: plan2.forward(x2, stream), 20, stream)
     t_p = _time(torch, lambda: [plan2.forward(x2[i:i + 1], stream) for i in range(4)], 20, stream)
-    out["c2_forward"] = {"batched_us": round(t_b * 1e3, 2), "per_poly_launch_us": round(t_p * 1e3, 2),
-                         "batched_limb_ntt_per_s": 144 / (t_b * 1e-3), "batched_over_plain": round(t_p / t_b, 3)}
+    out["c2_forward"] = {"batched_us": round(t_bc * 1e3, 2), "per_poly_launch_us": round(t_pc * 1e3, 2),
+                         "batched_limb_ntt_per_s": 144 / (t_bc * 1e-3),
+                         "batched_over_plain": round(t_pc / t_bc, 3),
+                         "warm_batched_us": round(t_b * 1e3, 2), "warm_per_poly_launch_us": round(t_p * 1e3, 2),
+                         "warm_batched_over_plain": round(t_p / t_b, 3),
+                         "note": "cold: rotating sets; warm: one 75.5 MB set, Infinity-Cache resident"}
     # C3 TFHE-shaped: 2048 x 2^10 u32 forward, MAC (6 rows x 2 cols), 684 inverse.
     N, Pn, rows, cols = 1 << 10, 2048, 6, 2
     q = synth.c3_prime()
@@ -355,6 +475,13 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
     def c3_cmux():
         p3.cmux(cm_out, ct, rot3, key4, 3, 11, stream)
 
+    # The 2048-operand forward alone: cold over 40 copies of the operands
+    # (336 MB, more than the Infinity Cache) and warm on one copy (8.4 MB).
+    sets3 = [a.clone() for _ in range(40)]
+    ctr3 = itertools.count()
+    t_fc = _time(torch, lambda: p3.forward(sets3[next(ctr3) % 40], stream), 80, stream)
+    t_fw = _time(torch, lambda: p3.forward(work, stream), 80, stream)
+    del sets3
     tb = _time(torch, c3_batched, 20, stream)
     tp = _time(torch, c3_plain, 3, stream)
     tf = _time(torch, c3_fused, 20, stream)
@@ -363,7 +490,31 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
     copy_ms = _time(torch, lambda: work.copy_(a), 20, stream)
     torch.cuda.synchronize()
     n3 = Pn + G * cols
-    out["c3_tfhe"] = {"batched_us": round(tb * 1e3, 2), "plain_us": round(tp * 1e3, 2),
+    # Algorithmic bytes (u32 words, N = 2^10): a limb transform reads and writes
+    # its 4 KiB (8 KiB); the MAC reads the 2048 operands and the 12 key rows and
+    # writes the 684 accumulators; the fused external product moves the same
+    # words as the MAC; the decomposing form and the CMux step read the 342 x 2
+    # ciphertext rows instead of the 2048 digit operands.
+    row_b = N * 4
+    b_fwd = Pn * 2 * row_b
+    b_mac = (Pn + rows * cols + G * cols) * row_b
+    b_inv = G * cols * 2 * row_b
+    b_dec = (G * 2 + rows * cols + G * cols) * row_b
+
+    def frac(b, ms):
+        return round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    out["c3_tfhe"] = {"forward_2048_cold_us": round(t_fc * 1e3, 2),
+                      "forward_2048_cold_hbm_frac": frac(b_fwd, t_fc),
+                      "forward_2048_cold_limb_ntt_per_s": Pn / (t_fc * 1e-3),
+                      "forward_2048_warm_us": round(t_fw * 1e3, 2),
+                      "forward_2048_warm_hbm_frac": frac(b_fwd, t_fw),
+                      "fwd_mac_inv_hbm_frac": frac(b_fwd + b_mac + b_inv, tb - copy_ms),
+                      "external_product_hbm_frac": frac(b_mac, tf),
+                      "external_product_decomposed_hbm_frac": frac(b_dec, td),
+                      "cmux_step_hbm_frac": frac(b_dec, tcm),
+                      "note": "8.4 MB of operands fit in the Infinity Cache: every figure but "
+                              "forward_2048_cold is warm",
+                      "batched_us": round(tb * 1e3, 2), "plain_us": round(tp * 1e3, 2),
                       "input_copy_us": round(copy_ms * 1e3, 2),
                       "batched_ntt_per_s": n3 / ((tb - copy_ms) * 1e-3),
                       "batched_over_plain": round(tp / tb, 2),
@@ -386,7 +537,8 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, x2, str
         out["c4_ragged"] = run_ragged(args, torch, ntt, synth, to_device, stream)
     if not args.no_serving:
         from paper_2410_05934_amd import serving
-        res = serving.sweep(args.serving_requests, [0.1, 0.3, 0.5, 0.9], 64 << 30, 4, args.seed, True)
+        res = serving.sweep(args.serving_requests, [0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.2], 64 << 30, 4,
+                            args.seed, True)
         keep = ("offered_rate", "achieved_req_per_s", "p50_ms", "p99_ms", "p99_ms_small",
                 "p99_ms_large", "mean_batch")
         out["c5_serving"] = {
@@ -508,9 +660,119 @@ def run_cpu_baseline(args):
         el = time.perf_counter() - t0
         if el >= args.cpu_seconds:
             break
+    # One core: forward + inverse of one of the polynomials (72 limb transforms)
+    # repeated for about a quarter of the time.
+    t1 = time.perf_counter()
+    reps1 = 0
+    while True:
+        oracle.inverse(oracle.forward(x[0:1], moduli, 1), moduli, 1)
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= args.cpu_seconds / 4:
+            break
     return {"value": 504 * steps / el, "unit": "limb-NTT/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} whole steps of the same workload (4x36x2^16, fwd+pointwise+inv+polymul), "
-                      f"{el:.1f} s, {cores} threads over (poly, limb) rows"}
+                      f"{el:.1f} s, {cores} threads over (poly, limb) rows",
+            "one_core": {"value": 72 * reps1 / el1, "unit": "limb-NTT/s", "cores": 1,
+                         "sample": f"{reps1} x forward + inverse of one 36-limb 2^16 polynomial, {el1:.1f} s"}}
+
+
+_CLS = {"ArF64S": "f64s", "ArF64L": "f64l", "ArI64": "i64"}
+
+
+def bench_name(symbol: str, log_n: int = 16):
+    """The library's per-launch timer name of a HIP kernel symbol as rocprofv3
+    prints it (for the kernels of the CKKS-shaped workload, N = 2^log_n), or None."""
+    import re
+    m = re.search(r"nttk::(\w+)<([^>]*)>", symbol)
+    if not m:
+        return None
+    kind, targs = m.group(1), [t.strip().replace("nttk::", "") for t in m.group(2).split(",")]
+    if kind == "col_kernel":
+        a, n1, inv, two = targs[:4]
+        return f"col_{'inv' if inv == 'true' else 'fwd'}_{_CLS[a]}_log{n1}{'_2pass' if two == 'true' else ''}"
+    if kind == "row_kernel":
+        a, n2, inv, two, rb = targs[:5]
+        pre = {"4": "row", "3": "row8", "2": "row4"}[rb]
+        return f"{pre}_{'inv' if inv == 'true' else 'fwd'}_{_CLS[a]}_log{n2}{'_2pass' if two == 'true' else ''}"
+    if kind == "polymul_row_kernel":
+        a, n2, two, rb = targs[:4]
+        fm = len(targs) > 4 and targs[4] == "true"
+        pre = ("fwdmul_row" if fm else "polymul_row") + ("8" if rb == "3" else "")
+        return f"{pre}_fwd_{_CLS[a]}_log{n2}{'_2pass' if two == 'true' else ''}"
+    if kind == "pointwise_kernel":
+        return f"pointwise_fwd_{_CLS[targs[0]]}_log{log_n}"
+    if kind in ("bconv_mfma_kernel", "bconv_f64_kernel", "bconv_kernel"):
+        w = "u32" if "unsigned int" in targs[0] else "u64"
+        mode = int(targs[-1])
+        base = ["bconv", "modup", "moddown"][mode]
+        form = {"bconv_mfma_kernel": "_mfma", "bconv_f64_kernel": "_f64", "bconv_kernel": ""}[kind]
+        return f"{base}{form}_fwd_{w}_log{log_n}"
+    return None
+
+
+def _per_dispatch(csv_path: str) -> dict:
+    """{kernel symbol: {counter: mean per dispatch (summed over instances)}, "_n": dispatches}."""
+    import csv
+    from collections import defaultdict
+    sums = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            k = r["Kernel_Name"]
+            sums[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k].add(r["Dispatch_Id"])
+    return {k: {**{c: v / len(disp[k]) for c, v in cs.items()}, "_n": len(disp[k])} for k, cs in sums.items()}
+
+
+def summarize_counters(args) -> None:
+    """Reduce rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE, the same two on the
+    calibration copy, and the VALU / LDS set) to profiles/counters.json: per
+    kernel, HBM bytes and VALU instructions per launch, keyed by the hash of the
+    kernel sources they were taken on."""
+    cal_f = _per_dispatch(args.cal_fetch_csv)
+    cal_w = _per_dispatch(args.cal_write_csv)
+    copy_bytes = float(1 << 30)
+    fcopy = max((v for v in cal_f.values()), key=lambda v: v.get("FETCH_SIZE", 0))["FETCH_SIZE"] * 1024
+    wcopy = max((v for v in cal_w.values()), key=lambda v: v.get("WRITE_SIZE", 0))["WRITE_SIZE"] * 1024
+    ff, wf = copy_bytes / fcopy, copy_bytes / wcopy
+    fetch = _per_dispatch(args.fetch_csv)
+    write = _per_dispatch(args.write_csv)
+    valu = _per_dispatch(args.valu_csv) if args.valu_csv else {}
+    kernels = {}
+    for sym in sorted(set(fetch) | set(write) | set(valu)):
+        name = bench_name(sym)
+        if name is None:
+            continue
+        rec = {"symbol": sym.split("(")[0].replace("void ", "").replace("nttk::", "")}
+        if sym in fetch and sym in write:
+            rec["launches_sampled"] = int(fetch[sym]["_n"])
+            rec["fetch_bytes_per_launch"] = round(fetch[sym]["FETCH_SIZE"] * 1024 * ff)
+            rec["write_bytes_per_launch"] = round(write[sym]["WRITE_SIZE"] * 1024 * wf)
+            rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        if sym in valu:
+            v = valu[sym]
+            for key, c in (("valu_insts_per_launch", "SQ_INSTS_VALU"), ("valu_active_quads_per_launch", "SQ_ACTIVE_INST_VALU"),
+                           ("lds_insts_per_launch", "SQ_INSTS_LDS"), ("lds_bank_conflict_cycles", "SQ_LDS_BANK_CONFLICT"),
+                           ("lds_active_cycles", "SQ_LDS_IDX_ACTIVE"), ("waves_per_launch", "SQ_WAVES"),
+                           ("gui_active_cycles_sum_xcc", "GRBM_GUI_ACTIVE")):
+                if c in v:
+                    rec[key] = round(v[c])
+            if "SQ_ACTIVE_INST_VALU" in v and "GRBM_GUI_ACTIVE" in v:
+                # rocprofv3's VALUBusy: quad-cycles of VALU work per CU over the
+                # busy cycles of one XCD (GRBM_GUI_ACTIVE is summed over 8 here)
+                rec["valu_busy_frac"] = round(v["SQ_ACTIVE_INST_VALU"] / 256 / (v["GRBM_GUI_ACTIVE"] / 8), 4)
+            if "SQ_LDS_IDX_ACTIVE" in v and "SQ_LDS_BANK_CONFLICT" in v and v["SQ_LDS_IDX_ACTIVE"] > 0:
+                rec["lds_conflicts_per_access"] = round(
+                    v["SQ_LDS_BANK_CONFLICT"] / max(1.0, v["SQ_LDS_IDX_ACTIVE"] - v["SQ_LDS_BANK_CONFLICT"]), 4)
+        kernels[name] = rec
+    out = {"source_hash": kernel_source_hash(),
+           "calibration": {"kernel": "device copy of 1 GiB (torch copy_)", "fetch_factor": round(ff, 4),
+                           "write_factor": round(wf, 4)},
+           "command": args.counters_command, "kernels": kernels}
+    with open(COUNTERS_PATH, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def calibrate_copy(gib: int = 1, reps: int = 4) -> None:
@@ -537,19 +799,33 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-file", default=None,
+                    help="load the tuning table from this file if it exists, else tune and save it there")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--row-radix8", action="store_true", help="radix-8 row passes")
     ap.add_argument("--unfused-step", action="store_true",
                     help="forward and pointwise product as two calls instead of ntt_forward_mul")
-    ap.add_argument("--serving-requests", type=int, default=3000)
+    ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--latency-only", action="store_true",
                     help="only run the single-polynomial 56-bit section (one JSON line) and exit")
     ap.add_argument("--latency-logn", type=int, nargs="*", default=None,
                     help="log2 N of the single-polynomial section (default 12 .. 16)")
+    ap.add_argument("--summarize-counters", action="store_true",
+                    help="reduce rocprofv3 counter CSVs (--fetch-csv, --write-csv, --cal-fetch-csv, "
+                         "--cal-write-csv, --valu-csv) to profiles/counters.json and exit")
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--cal-fetch-csv")
+    ap.add_argument("--cal-write-csv")
+    ap.add_argument("--valu-csv")
+    ap.add_argument("--counters-command", default="", help="the rocprofv3 commands, recorded in the JSON")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return

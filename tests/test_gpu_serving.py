@@ -93,3 +93,24 @@ def test_host_memory_requests_and_a_small_budget():
     for req, g in zip(reqs, got):
         assert np.array_equal(g, _want(req))
     assert c["max_inflight_bytes"] <= big + (1 << 20)
+
+
+def test_serving_mix_at_full_size():
+    """The serving configuration itself: 70% 1..64 polymul pairs at 2^10 over the
+    32-bit prime, 30% one pair at 2^16 over 8..36 of the 50-bit primes, each with
+    its own inputs; continuous batching on 4 streams against the serial server
+    and the oracle, word for word."""
+    reqs = []
+    for i, r in enumerate(synth.c5_requests(7, 40, 1000.0)):
+        a = synth.uniform_poly(r.seed, r.moduli, r.pairs, r.N)
+        b = synth.uniform_poly(r.seed + 1, r.moduli, r.pairs, r.N)
+        reqs.append((ntt.REQ_POLYMUL, r.N, r.moduli, r.word_bits, r.pairs, a, b))
+    assert any(q[1] == 1 << 16 and len(q[2]) >= 30 for q in reqs)
+    assert any(q[1] == 1 << 10 and q[4] >= 40 for q in reqs)
+    mixed, infos, c = _run(reqs, 0, streams=4, budget=64 << 30)
+    alone, _, _ = _run(reqs, ntt.SERVER_SERIAL, streams=1, budget=64 << 30)
+    assert max(x["batched_with"] for x in infos) > 1, "the mix should have batched something"
+    for req, m, s in zip(reqs, mixed, alone):
+        w = oracle.polymul(req[5], req[6], req[2])
+        assert np.array_equal(m, w)
+        assert np.array_equal(s, w)
