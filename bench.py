@@ -327,66 +327,74 @@ def run_gpu(args):
     if not args.no_aux:
         import itertools
         ctr = itertools.count()
-        # Automorphism sigma_5 of every limb (coefficient domain, then the forward
-        # transform's slot order) from the rotating sets into two output buffers:
-        # algorithmic bytes = every word read once and written once.
-        outs = [empty_device((P, L, N), 64) for _ in range(2)]
-        auto = {}
-        k_inv5 = pow(5, -1, 2 * N)
-        for name, k, tr in (("coefficient", 5, False), ("coefficient_k_inv5", k_inv5, False),
-                            ("transformed", 5, True)):
-            def call(k=k, tr=tr):
-                j = next(ctr)
-                plan.automorph(outs[j % 2], X[j % args.sets], k, tr, stream)
-            t = _time(torch, call, 4 * args.sets, stream)
-            auto[name] = {"us": round(t * 1e3, 2),
-                          "alg_GBps": round(coeff_bytes / (t * 1e-3) / 1e9, 1),
-                          "hbm_frac": round(coeff_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        del outs
-        _log(f"[bench] automorphism k=5: {auto}")
-        extra["c2_automorph_k5"] = auto
-        # Basis conversion of the 4 x 36-limb polynomials to 36 other 50-bit primes:
-        # 36 x (36 + 5) Shoup products per coefficient (five chunks of output moduli).
         dst = synth.primes_below(1 << 50, 1 << 17, 2 * L)[L:]
-        conv = ntt.BasisConversion(N, moduli, dst, 64)
-        yb = empty_device((P, L, N), 64)
+        if want(args, "automorph"):
+            # Automorphism sigma_5 of every limb (coefficient domain, then the forward
+            # transform's slot order) from the rotating sets into two output buffers:
+            # algorithmic bytes = every word read once and written once.
+            outs = [empty_device((P, L, N), 64) for _ in range(2)]
+            auto = {}
+            k_inv5 = pow(5, -1, 2 * N)
+            for name, k, tr in (("coefficient", 5, False), ("coefficient_k_inv5", k_inv5, False),
+                                ("transformed", 5, True)):
+                def call(k=k, tr=tr):
+                    j = next(ctr)
+                    plan.automorph(outs[j % 2], X[j % args.sets], k, tr, stream)
+                t = _time(torch, call, 4 * args.sets, stream)
+                auto[name] = {"us": round(t * 1e3, 2),
+                              "alg_GBps": round(coeff_bytes / (t * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(coeff_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del outs
+            _log(f"[bench] automorphism k=5: {auto}")
+            extra["c2_automorph_k5"] = auto
+        if want(args, "bconv"):
+            # Basis conversion of the 4 x 36-limb polynomials to 36 other 50-bit primes:
+            # 36 x (36 + 5) Shoup products per coefficient (five chunks of output moduli).
+            conv = ntt.BasisConversion(N, moduli, dst, 64)
+            yb = empty_device((P, L, N), 64)
 
-        def bcall():
-            conv(yb, X[next(ctr) % args.sets], stream)
-        t = _time(torch, bcall, 2 * args.sets, stream)
-        prods = P * N * L * (L + (L + 7) // 8)
-        extra["c2_bconv_36_to_36"] = {"us": round(t * 1e3, 2),
-                                      "modmul_per_s": prods / (t * 1e-3),
-                                      "alg_GBps": round(2 * P * L * N * 8 / (t * 1e-3) / 1e9, 1)}
-        del yb, conv
-        _log(f"[bench] basis conversion 36 -> 36: {extra['c2_bconv_36_to_36']}")
-        # ModUp of the 4 x 36-limb polynomials to Q u P with 36 special primes (the
-        # next 36 primes = 1 mod 2^17 below the CKKS ones), and ModDown back: each
-        # reads 36 (up) or 72 (down) limbs and writes 72 or 36, 108 limb-rows of
-        # 2^16 words per polynomial.  Two wide buffers alternate.
-        ext = ntt.BasisExtension(N, moduli, dst, 64)
-        ups = [empty_device((P, 2 * L, N), 64) for _ in range(2)]
-        dn = empty_device((P, L, N), 64)
-        for j in range(2):
-            ext.mod_up(ups[j], X[j], stream)
+            def bcall():
+                conv(yb, X[next(ctr) % args.sets], stream)
+            t = _time(torch, bcall, 2 * args.sets, stream)
+            prods = P * N * L * (L + (L + 7) // 8)
+            extra["c2_bconv_36_to_36"] = {"us": round(t * 1e3, 2),
+                                          "modmul_per_s": prods / (t * 1e-3),
+                                          "alg_GBps": round(2 * P * L * N * 8 / (t * 1e-3) / 1e9, 1)}
+            del yb, conv
+            _log(f"[bench] basis conversion 36 -> 36: {extra['c2_bconv_36_to_36']}")
+        if want(args, "modup"):
+            # ModUp of the 4 x 36-limb polynomials to Q u P with 36 special primes (the
+            # next 36 primes = 1 mod 2^17 below the CKKS ones), and ModDown back: each
+            # reads 36 (up) or 72 (down) limbs and writes 72 or 36, 108 limb-rows of
+            # 2^16 words per polynomial.  Two wide buffers alternate.
+            ext = ntt.BasisExtension(N, moduli, dst, 64)
+            ups = [empty_device((P, 2 * L, N), 64) for _ in range(2)]
+            dn = empty_device((P, L, N), 64)
+            for j in range(2):
+                ext.mod_up(ups[j], X[j], stream)
 
-        def upcall():
-            j = next(ctr)
-            ext.mod_up(ups[j % 2], X[j % args.sets], stream)
+            def upcall():
+                j = next(ctr)
+                ext.mod_up(ups[j % 2], X[j % args.sets], stream)
 
-        def downcall():
-            ext.mod_down(dn, ups[next(ctr) % 2], stream)
-        ks_bytes = P * 3 * L * N * 8
-        ks = {}
-        for name, fn in (("mod_up", upcall), ("mod_down", downcall)):
-            t = _time(torch, fn, 2 * args.sets, stream)
-            ks[name] = {"us": round(t * 1e3, 2), "alg_GBps": round(ks_bytes / (t * 1e-3) / 1e9, 1),
-                        "hbm_frac": round(ks_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        del ups, dn, ext
-        _log(f"[bench] ModUp / ModDown 36 + 36: {ks}")
-        extra["c2_modup_moddown_36_36"] = ks
+            def downcall():
+                ext.mod_down(dn, ups[next(ctr) % 2], stream)
+            ks_bytes = P * 3 * L * N * 8
+            ks = {}
+            for name, fn in (("mod_up", upcall), ("mod_down", downcall)):
+                t = _time(torch, fn, 2 * args.sets, stream)
+                ks[name] = {"us": round(t * 1e3, 2), "alg_GBps": round(ks_bytes / (t * 1e-3) / 1e9, 1),
+                            "hbm_frac": round(ks_bytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del ups, dn, ext
+            _log(f"[bench] ModUp / ModDown 36 + 36: {ks}")
+            extra["c2_modup_moddown_36_36"] = ks
         extra.update(run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan, X, stream))
     return value, ms_per_step, roofline, extra
+
+
+def want(args, section: str) -> bool:
+    """Whether an auxiliary section runs (--sections restricts them)."""
+    return args.sections is None or section in args.sections.split(",")
 
 
 def _time(torch, fn, reps, stream):
@@ -410,6 +418,27 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, X, stre
     import itertools
     ctr = itertools.count()
     x2 = X[0]
+    if want(args, "batched"):
+        run_batched_vs_plain(args, torch, plan2, X, x2, ctr, stream, out)
+    if want(args, "c3"):
+        run_c3(args, torch, ntt, synth, to_device, empty_device, stream, out)
+    if want(args, "c1"):
+        N = 1 << 10
+        q1 = synth.c1_prime(0)
+        p1 = ntt.Plan(N, [q1], 32)
+        x1 = to_device(synth.uniform_poly(7, [q1], 1, N), 32)
+        t1 = _time(torch, lambda: (p1.forward(x1, stream), p1.inverse(x1, stream)), 200, stream)
+        out["c1_fwd_inv_us"] = round(t1 * 1e3, 2)
+    if want(args, "latency"):
+        out["single_polynomial_56bit"] = run_latency(args, torch, ntt, synth, to_device, stream)
+    if not args.no_ragged and want(args, "ragged"):
+        out["c4_ragged"] = run_ragged(args, torch, ntt, synth, to_device, stream)
+    if not args.no_serving and want(args, "serving"):
+        run_serving(args, out)
+    return out
+
+
+def run_batched_vs_plain(args, torch, plan2, X, x2, ctr, stream, out):
 
     def cold_batched():
         plan2.forward(X[next(ctr) % args.sets], stream)
@@ -428,7 +457,12 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, X, stre
                          "warm_batched_us": round(t_b * 1e3, 2), "warm_per_poly_launch_us": round(t_p * 1e3, 2),
                          "warm_batched_over_plain": round(t_p / t_b, 3),
                          "note": "cold: rotating sets; warm: one 75.5 MB set, Infinity-Cache resident"}
-    # C3 TFHE-shaped: 2048 x 2^10 u32 forward, MAC (6 rows x 2 cols), 684 inverse.
+
+
+def run_c3(args, torch, ntt, synth, to_device, empty_device, stream, out):
+    """TFHE-shaped: 2048 x 2^10 u32 forward, MAC (6 rows x 2 cols), 684 inverse;
+    the fused external product, its decomposing form and the CMux step."""
+    import itertools
     N, Pn, rows, cols = 1 << 10, 2048, 6, 2
     q = synth.c3_prime()
     p3 = ntt.Plan(N, [q], 32)
@@ -526,30 +560,22 @@ def run_aux(args, torch, ntt, synth, np, to_device, empty_device, plan2, X, stre
                       "external_product_decomposed_ntt_per_s": (G * rows + G * cols) / (td * 1e-3),
                       "cmux_step_us": round(tcm * 1e3, 2),
                       "cmux_per_s": G / (tcm * 1e-3)}
-    # C1 latency: one 2^10 forward + inverse, u32.
-    q1 = synth.c1_prime(0)
-    p1 = ntt.Plan(N, [q1], 32)
-    x1 = to_device(synth.uniform_poly(7, [q1], 1, N), 32)
-    t1 = _time(torch, lambda: (p1.forward(x1, stream), p1.inverse(x1, stream)), 200, stream)
-    out["c1_fwd_inv_us"] = round(t1 * 1e3, 2)
-    out["single_polynomial_56bit"] = run_latency(args, torch, ntt, synth, to_device, stream)
-    if not args.no_ragged:
-        out["c4_ragged"] = run_ragged(args, torch, ntt, synth, to_device, stream)
-    if not args.no_serving:
-        from paper_2410_05934_amd import serving
-        res = serving.sweep(args.serving_requests, [0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.2], 64 << 30, 4,
-                            args.seed, True)
-        keep = ("offered_rate", "achieved_req_per_s", "p50_ms", "p99_ms", "p99_ms_small",
-                "p99_ms_large", "mean_batch")
-        out["c5_serving"] = {
-            "requests": res["requests"], "budget_bytes": res["budget_bytes"], "streams": res["streams"],
-            "batched_capacity_req_per_s": res["batched"]["capacity_req_per_s"],
-            "serial_capacity_req_per_s": res["serial"]["capacity_req_per_s"],
-            "batched_over_serial_capacity": res["batched_over_serial_capacity"],
-            "batched": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["batched"]["open_loop"]],
-            "serial": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["serial"]["open_loop"]],
-        }
-    return out
+
+
+def run_serving(args, out):
+    from paper_2410_05934_amd import serving
+    res = serving.sweep(args.serving_requests, [0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.2], 64 << 30, 4,
+                        args.seed, True)
+    keep = ("offered_rate", "achieved_req_per_s", "p50_ms", "p99_ms", "p99_ms_small",
+            "p99_ms_large", "mean_batch")
+    out["c5_serving"] = {
+        "requests": res["requests"], "budget_bytes": res["budget_bytes"], "streams": res["streams"],
+        "batched_capacity_req_per_s": res["batched"]["capacity_req_per_s"],
+        "serial_capacity_req_per_s": res["serial"]["capacity_req_per_s"],
+        "batched_over_serial_capacity": res["batched_over_serial_capacity"],
+        "batched": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["batched"]["open_loop"]],
+        "serial": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["serial"]["open_loop"]],
+    }
 
 
 def run_latency(args, torch, ntt, synth, to_device, stream):
@@ -802,6 +828,9 @@ def main():
     ap.add_argument("--tune-file", default=None,
                     help="load the tuning table from this file if it exists, else tune and save it there")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--sections", default=None,
+                    help="comma list of auxiliary sections to run (automorph, bconv, modup, batched, "
+                         "c3, c1, latency, ragged, serving); default all")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--row-radix8", action="store_true", help="radix-8 row passes")
     ap.add_argument("--unfused-step", action="store_true",
