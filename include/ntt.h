@@ -191,6 +191,12 @@ typedef struct ntt_bconv_s* ntt_bconv_t;
  * L and M (the fp64 bound and N >= 32 still apply); the words are the same. */
 #define NTT_BCONV_NO_MFMA 1u
 #define NTT_BCONV_MFMA 2u
+/* With at most 48 source and 48 target moduli the matrix-core form keeps each
+ * wave's constant operands in registers for the whole launch (one wave per 4
+ * targets beside four waves that form the digits, each workgroup walking a run
+ * of 32-coefficient tiles); NTT_BCONV_NO_WS keeps the streaming form, which
+ * reloads them per tile.  The words are the same. */
+#define NTT_BCONV_NO_WS 4u
 ntt_status ntt_bconv_create(ntt_bconv_t* out, uint32_t N, const uint64_t* src_moduli, uint32_t L,
                             const uint64_t* dst_moduli, uint32_t M, uint32_t word_bits,
                             uint32_t flags);

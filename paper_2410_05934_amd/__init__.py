@@ -35,6 +35,7 @@ FLAG_VALIDATE = 1 << 20
 AUTOMORPH_TRANSFORMED = 1
 BCONV_NO_MFMA = 1
 BCONV_MFMA = 2
+BCONV_NO_WS = 4
 
 STATUS = {0: "NTT_OK", 1: "NTT_EINVAL", 2: "NTT_ENOTPRIME", 3: "NTT_ENOROOT", 4: "NTT_ERANGE",
           5: "NTT_ENOMEM", 6: "NTT_EDEVICE", 7: "NTT_EBUSY", 8: "NTT_ETIMEOUT"}
@@ -186,18 +187,20 @@ class BasisConversion:
     """RNS basis conversion from src_moduli (L) to dst_moduli (M) for length N:
     out[b][j] = sum_i [x_i (Q/q_i)^-1]_(q_i) (Q/q_i) mod p_j (X + alpha Q, 0 <= alpha < L)."""
 
-    def __init__(self, N: int, src_moduli, dst_moduli, word_bits: int = 64, mfma=None):
+    def __init__(self, N: int, src_moduli, dst_moduli, word_bits: int = 64, mfma=None,
+                 stationary: bool = True):
         """mfma: None lets the library choose, True asks for the int8 matrix cores
-        wherever they apply, False keeps the vector units."""
+        wherever they apply, False keeps the vector units.  stationary=False keeps
+        the matrix-core form that reloads its constant operands per tile."""
         self.N, self.word_bits = int(N), int(word_bits)
         self.L, self.M = len(src_moduli), len(dst_moduli)
         src = (_u64 * self.L)(*[int(q) for q in src_moduli])
         dst = (_u64 * self.M)(*[int(p) for p in dst_moduli])
         self._h = _vp()
+        flags = (0 if mfma is None else (BCONV_MFMA if mfma else BCONV_NO_MFMA)) | \
+            (0 if stationary else BCONV_NO_WS)
         _check(lib().ntt_bconv_create(ctypes.byref(self._h), self.N, src, self.L, dst, self.M,
-                                      self.word_bits,
-                                      0 if mfma is None else (BCONV_MFMA if mfma else BCONV_NO_MFMA)),
-               "ntt_bconv_create")
+                                      self.word_bits, flags), "ntt_bconv_create")
 
     def _batch(self, t, rows: int, name: str) -> int:
         if not t.is_cuda or not t.is_contiguous():
@@ -235,16 +238,17 @@ class BasisExtension:
     BConv_{Q->P}(x)); mod_down: x[b][L + K][N] -> out[b][L][N] with
     out_i = (x_i - BConv_{P->Q}(x_P)_i) P^-1 mod q_i."""
 
-    def __init__(self, N: int, q_moduli, p_moduli, word_bits: int = 64, mfma=None):
+    def __init__(self, N: int, q_moduli, p_moduli, word_bits: int = 64, mfma=None,
+                 stationary: bool = True):
         self.N, self.word_bits = int(N), int(word_bits)
         self.L, self.K = len(q_moduli), len(p_moduli)
         qs = (_u64 * self.L)(*[int(q) for q in q_moduli])
         ps = (_u64 * self.K)(*[int(p) for p in p_moduli])
         self._h = _vp()
+        flags = (0 if mfma is None else (BCONV_MFMA if mfma else BCONV_NO_MFMA)) | \
+            (0 if stationary else BCONV_NO_WS)
         _check(lib().ntt_basis_ext_create(ctypes.byref(self._h), self.N, qs, self.L, ps, self.K,
-                                          self.word_bits,
-                                          0 if mfma is None else (BCONV_MFMA if mfma else BCONV_NO_MFMA)),
-               "ntt_basis_ext_create")
+                                          self.word_bits, flags), "ntt_basis_ext_create")
 
     def _batch(self, t, rows: int, name: str) -> int:
         return BasisConversion._batch(self, t, rows, name)

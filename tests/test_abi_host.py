@@ -110,7 +110,7 @@ def test_plan_create_rejects_bad_moduli_before_touching_the_device():
     assert lib.ntt_plan_create(ctypes.byref(h), 1024, arr1, 0, 32, 0) == 1
     assert lib.ntt_plan_create(ctypes.byref(h), 1024, arr1, 1, 32, ntt.flag_split(7)) == 1
     src = (ctypes.c_uint64 * 1)(536881153)
-    assert lib.ntt_bconv_create(ctypes.byref(h), 1024, src, 1, src, 1, 64, 4) == 1
+    assert lib.ntt_bconv_create(ctypes.byref(h), 1024, src, 1, src, 1, 64, 8) == 1
     assert b"flags" in lib.ntt_last_error()
     assert lib.ntt_bconv_create(ctypes.byref(h), 1024, src, 1, src, 1, 64, 3) == 1
     assert b"exclusive" in lib.ntt_last_error()

@@ -105,3 +105,26 @@ def test_bconv_matrix_core_form_at_n_32_and_edge_values():
         x[1, i] = q - 1
     got = _run(ntt.BasisConversion(N, src, dst, 64, mfma=True), x, 6, 64)
     assert np.array_equal(got, oracle.bconv(x, src, dst))
+
+
+@pytest.mark.parametrize("L,M,logn,batch", [(1, 1, 5, 3), (3, 4, 6, 2), (9, 17, 12, 3), (36, 36, 10, 5),
+                                            (37, 48, 7, 2), (64, 47, 8, 2), (64, 49, 7, 1), (33, 12, 9, 3),
+                                            (2, 16, 16, 1)])
+def test_bconv_weights_stationary_form_equals_streaming_form(L, M, logn, batch):
+    """The matrix-core form that keeps constant operands in registers (up to 48
+    targets: one wave per 4 targets beside four digit-forming waves, workgroups
+    walking 32-coefficient tiles) gives the words of the form that reloads them
+    per tile, and the oracle's."""
+    pool = synth.primes_below(1 << 50, 1 << 17, L + M)
+    src, dst = pool[:L], pool[L:]
+    N = 1 << logn
+    x = synth.uniform_poly(97 + L + M, src, batch, N)
+    x[0, :, :2] = 0
+    for i, q in enumerate(src):
+        x[-1, i, -2:] = q - 1
+    ws = _run(ntt.BasisConversion(N, src, dst, 64, mfma=True), x, M, 64)
+    st = _run(ntt.BasisConversion(N, src, dst, 64, mfma=True, stationary=False), x, M, 64)
+    assert np.array_equal(ws, st)
+    k = min(N, 256)
+    assert np.array_equal(ws[:, :, :k], oracle.bconv(x[:, :, :k], src, dst))
+    assert np.array_equal(ws[:, :, -k:], oracle.bconv(x[:, :, -k:], src, dst))

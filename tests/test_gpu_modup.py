@@ -48,7 +48,7 @@ CASES = [(1, 1, False), (3, 5, False), (9, 17, False), (20, 3, False), (36, 36, 
 
 @pytest.mark.parametrize("word_bits", [32, 64])
 @pytest.mark.parametrize("L,K,wide", CASES)
-@pytest.mark.parametrize("mfma", [None, False, True])
+@pytest.mark.parametrize("mfma", [None, False, True, "streaming"])
 @pytest.mark.parametrize("logn", [1, 6, 11])
 def test_mod_up_and_down_match_oracle(word_bits, L, K, wide, mfma, logn):
     if word_bits == 32 and wide:
@@ -57,7 +57,10 @@ def test_mod_up_and_down_match_oracle(word_bits, L, K, wide, mfma, logn):
         pytest.skip("the matrix-core form needs fp64-sized moduli and N >= 32")
     N = 1 << logn
     q, p = _bases(word_bits, L, K, wide)
-    ext = ntt.BasisExtension(N, q, p, word_bits, mfma=mfma)
+    if mfma == "streaming":
+        ext = ntt.BasisExtension(N, q, p, word_bits, mfma=True, stationary=False)
+    else:
+        ext = ntt.BasisExtension(N, q, p, word_bits, mfma=mfma)
     x = synth.uniform_poly(300 + L + K + logn, q, 3, N)
     assert np.array_equal(_up(ext, x, word_bits), oracle.mod_up(x, q, p))
     xw = synth.uniform_poly(400 + L + K + logn, q + p, 3, N)
