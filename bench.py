@@ -737,17 +737,19 @@ def bench_name(symbol: str, log_n: int = 16):
     return None
 
 
-def _per_dispatch(csv_path: str) -> dict:
-    """{kernel symbol: {counter: mean per dispatch (summed over instances)}, "_n": dispatches}."""
+def _per_dispatch(csv_paths: str) -> dict:
+    """{kernel symbol: {counter: mean per dispatch (summed over instances)}, "_n": dispatches}
+    over one or more comma-separated rocprofv3 counter CSVs."""
     import csv
     from collections import defaultdict
     sums = defaultdict(lambda: defaultdict(float))
     disp = defaultdict(set)
-    with open(csv_path) as f:
-        for r in csv.DictReader(f):
-            k = r["Kernel_Name"]
-            sums[k][r["Counter_Name"]] += float(r["Counter_Value"])
-            disp[k].add(r["Dispatch_Id"])
+    for path in csv_paths.split(","):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = r["Kernel_Name"]
+                sums[k][r["Counter_Name"]] += float(r["Counter_Value"])
+                disp[k].add((path, r["Dispatch_Id"]))
     return {k: {**{c: v / len(disp[k]) for c, v in cs.items()}, "_n": len(disp[k])} for k, cs in sums.items()}
 
 
