@@ -202,7 +202,7 @@ def run_gpu(args):
     C = [torch.zeros((2, L, N), dtype=torch.int64, device="cuda") for _ in range(args.sets)]
     stream = torch.cuda.current_stream()
 
-    def step(i, unfused=args.unfused_step):
+    def step(i, unfused=args.unfused_step, noalloc=False):
         r = i % args.sets
         x = X[r]
         if unfused:
@@ -213,7 +213,10 @@ def run_gpu(args):
             # products written by the row pass that finishes the transforms
             plan.forward_mul(PW[r], x[0:2], x[2:4], stream)
         plan.inverse(x, stream)
-        plan.polymul(C[r], x[0:2], x[2:4], stream)
+        if noalloc:
+            plan.polymul_noalloc(C[r], x[0:2], x[2:4], stream)
+        else:
+            plan.polymul(C[r], x[0:2], x[2:4], stream)
 
     transforms_per_step = 144 + 144 + 144 + 72
     for i in range(args.warmup):
@@ -267,6 +270,14 @@ def run_gpu(args):
     t1.record(stream)
     torch.cuda.synchronize()
     ms_other = t0.elapsed_time(t1) / args.steps
+    # The same steps with the product's workspace from the library's fixed per-GPU
+    # scratch (ntt_polymul_noalloc) instead of the stream-ordered pool.
+    t0.record(stream)
+    for i in range(args.steps):
+        step(i, noalloc=True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_noalloc = t0.elapsed_time(t1) / args.steps
 
     import itertools
     rot = itertools.count()
@@ -312,6 +323,7 @@ def run_gpu(args):
              "step_time_percentiles": percentiles(step_ms),
              ("ms_per_step_fused_forward_mul" if args.unfused_step else "ms_per_step_unfused"):
                  round(ms_other, 4),
+             "ms_per_step_polymul_noalloc": round(ms_noalloc, 4),
              "rotating_sets": args.sets, "split_used": plan.split_for(P), "tuned": tuned}
     coeff_bytes = 144 * 2 * N * 8
     whole = {}
