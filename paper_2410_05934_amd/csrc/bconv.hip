@@ -353,8 +353,9 @@ __global__ void __launch_bounds__(256) bconv_mfma_kernel(BconvArgs a) {
 //     while the owners work on tile t.
 // So the matrix work of the owners and the vector work of the helpers run at
 // the same time on each SIMD; one barrier per tile separates the buffers.
-// Measured on 36 -> 36 limbs of 4 x 2^16 coefficients: 61 us, against 151 us
-// for the streaming form below (which reloads constant operands per row tile).
+// Measured on 36 -> 36 limbs of 4 x 2^16 coefficients: 57 us, against 151 us
+// for the streaming form above (bconv_mfma_kernel, which reloads the constant
+// operands per row tile); ModUp 61 us, ModDown 81-88 us.
 constexpr int kWsMaxTiles = 12;
 constexpr uint32_t kWsMaxLimbs = 48;  // 24 k-steps of constant operands in registers
 constexpr uint32_t kWsHelpers = 4;
