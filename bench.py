@@ -579,12 +579,17 @@ def run_serving(args, out):
     res = serving.sweep(args.serving_requests, [0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.2], 64 << 30, 4,
                         args.seed, True)
     keep = ("offered_rate", "achieved_req_per_s", "p50_ms", "p99_ms", "p99_ms_small",
-            "p99_ms_large", "mean_batch")
+            "p99_ms_large", "mean_batch", "mean_batch_large")
     out["c5_serving"] = {
         "requests": res["requests"], "budget_bytes": res["budget_bytes"], "streams": res["streams"],
         "batched_capacity_req_per_s": res["batched"]["capacity_req_per_s"],
+        "batched_burst_launches": res["batched"]["burst"]["launches"],
+        "merged_capacity_req_per_s": res["merged"]["capacity_req_per_s"],
+        "merged_burst_launches": res["merged"]["burst"]["launches"],
+        "merged_burst_merged_launches": res["merged"]["burst"]["merged_launches"],
         "serial_capacity_req_per_s": res["serial"]["capacity_req_per_s"],
         "batched_over_serial_capacity": res["batched_over_serial_capacity"],
+        "merged_over_batched_capacity": res["merged_over_batched_capacity"],
         "batched": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["batched"]["open_loop"]],
         "serial": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["serial"]["open_loop"]],
     }

@@ -448,6 +448,7 @@ typedef struct {
   uint64_t plans_cached;
   uint64_t arena_bytes;         /* staging arenas held now (never above the budget) */
   uint64_t max_arena_bytes;     /* high-water mark of arena_bytes */
+  uint64_t merged_launches;     /* launches whose requests had different moduli */
 } ntt_server_counters;
 
 typedef struct ntt_server_s* ntt_server_t;
@@ -456,12 +457,17 @@ typedef struct ntt_server_s* ntt_server_t;
 #define NTT_SERVER_SERIAL (1u << 0)   /* one request at a time, FIFO, no batching: the baseline */
 #define NTT_SERVER_DRY_RUN (1u << 1)  /* no device work: a batch "completes" after a modelled
                                          time; admission/batching logic testable without a GPU */
+#define NTT_SERVER_MERGE_MODULI (1u << 2) /* also batch requests whose moduli differ but share
+                                           one arithmetic class (one launch over their limbs) */
 
 /* Create a server: a host thread that admits requests while their device bytes
- * fit in budget_bytes (HBM admission), groups admitted requests of the same
- * shape (op, N, width, moduli) into one launch (continuous batching: requests
- * that arrive while others run join the next launch), and keeps up to
- * n_streams launches in flight on separate streams.  Plans and their twiddle
+ * fit in budget_bytes (HBM admission), groups admitted requests into one launch
+ * (continuous batching: requests that arrive while others run join the next
+ * launch), and keeps up to n_streams launches in flight on separate streams.
+ * Requests share a launch when op, N, word width, memory kind and moduli match;
+ * with NTT_SERVER_MERGE_MODULI also when only the moduli differ and all of
+ * them fall in one arithmetic class (at most 4096 limb-rows per such launch).
+ * A submit checks each distinct modulus once per server.  Plans and their twiddle
  * tables stay resident for the server's life.  max_batch caps the polynomials
  * per launch (0 = 4096); a launch also takes at most 64 requests.  Batched
  * operands are staged in a per-stream device arena that grows on demand and
@@ -473,9 +479,9 @@ ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t 
 
 /* Queue a request; *id identifies it.  A request larger than the budget is
  * rejected here with NTT_ENOMEM, one of batch * L * N >= 2^32 words with
- * NTT_EINVAL.  A launch gathers requests of one shape only while their words
- * stay below 2^32 (the library's per-call limit), so a request that succeeds
- * alone also succeeds in any mix. */
+ * NTT_EINVAL.  A launch gathers requests only while their words stay below
+ * 2^32 (the library's per-call limit), so a request that succeeds alone also
+ * succeeds in any mix; its result is the same word for word. */
 ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id);
 
 /* Wait for request `id` (timeout_ms < 0: forever); fills *info and forgets the

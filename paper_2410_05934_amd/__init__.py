@@ -20,7 +20,7 @@ __all__ = ["Plan", "NTTError", "lib", "check_modulus", "find_root", "library_pat
            "RaggedBatch", "batch_ragged", "debug_wait_limit", "BasisConversion", "OP_FORWARD", "OP_INVERSE", "OP_POLYMUL", "RAGGED_NO_GRAPH", "RAGGED_IN_WORKGROUP",
            "ragged_row_log", "tune_split", "tune_ragged", "tune_save", "tune_load", "tune_clear",
            "Server", "REQ_POLYMUL", "REQ_FORWARD", "REQ_INVERSE", "REQ_DEVICE", "REQ_HOST",
-           "SERVER_SERIAL", "SERVER_DRY_RUN"]
+           "SERVER_SERIAL", "SERVER_DRY_RUN", "SERVER_MERGE_MODULI"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_PKG, "libntt.so")
@@ -319,7 +319,7 @@ def tune_clear() -> None:
 
 REQ_POLYMUL, REQ_FORWARD, REQ_INVERSE = 0, 1, 2
 REQ_DEVICE, REQ_HOST = 0, 1
-SERVER_SERIAL, SERVER_DRY_RUN = 1, 2
+SERVER_SERIAL, SERVER_DRY_RUN, SERVER_MERGE_MODULI = 1, 2, 4
 
 
 class _Request(ctypes.Structure):
@@ -339,7 +339,7 @@ class _ServerCounters(ctypes.Structure):
     _fields_ = [(n, _u64) for n in ("submitted", "completed", "rejected", "launches",
                                     "max_inflight_bytes", "max_inflight_requests",
                                     "budget_bytes", "plans_cached", "arena_bytes",
-                                    "max_arena_bytes")]
+                                    "max_arena_bytes", "merged_launches")]
 
 
 class Server:

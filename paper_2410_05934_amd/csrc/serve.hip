@@ -3,10 +3,16 @@
 // A host thread owns the device side.  Requests wait in a FIFO; the thread
 // admits the oldest request whose device bytes fit under the HBM budget
 // (bytes of requests already in flight are still held), then pulls every
-// other waiting request of the same shape (op, N, word width, moduli) that
-// also fits, up to max_batch polynomials, and issues them as ONE launch:
-// gather kernel -> the library's batched transform/polymul -> scatter kernel,
-// on one of n_streams streams.  Requests that arrive while launches run are
+// other waiting request that can share its launch and also fits, up to
+// max_batch polynomials, and issues them as ONE launch: gather kernel -> the
+// library's batched transform/polymul -> scatter kernel, on one of n_streams
+// streams.  Requests share a launch when they have the same shape (op, N, word
+// width, memory kind, moduli).  With NTT_SERVER_MERGE_MODULI the moduli may
+// differ as long as every modulus of both requests is in the same arithmetic
+// class (the CKKS-shaped requests of a serving mix each carry their own number
+// of limbs).  Such a launch runs over one virtual plan whose limbs are the
+// requests' limbs laid end to end ([sum batch_i L_i][N], the gathered layout),
+// with the limb constants gathered on the device from the requests' own plans.  Requests that arrive while launches run are
 // admitted as memory and stream slots free up, so their work overlaps on the
 // device.  Plans (and their twiddle tables) are created on first use and stay
 // resident.  The batched arithmetic is the same per polynomial as alone, so a
@@ -25,6 +31,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <tuple>
 #include <unordered_map>
@@ -42,11 +49,15 @@ double now_s() {
 constexpr int kPollUs = 4;       // completion polling interval of the server thread
 constexpr uint64_t kMaxLaunchWords = 1ull << 32;  // words per library call: batch * L * N below this
 constexpr int kMaxCopies = 96;  // descriptors per gather/scatter launch (kernel-argument payload)
+constexpr uint64_t kMaxMergedLimbs = 4096;  // limb-rows of a launch over requests of different moduli
 
+// Copy n64 8-byte units; with period != 0 the source repeats every `period`
+// units (dst[i] = src[i % period]: a limb table replicated per polynomial).
 struct CopyDesc {
   uint64_t* dst;
   const uint64_t* src;
   uint64_t n64;  // 8-byte units
+  uint64_t period;
 };
 struct CopyList {
   CopyDesc d[kMaxCopies];
@@ -55,6 +66,23 @@ struct CopyList {
 
 __global__ void copy_list_kernel(CopyList list) {
   const CopyDesc c = list.d[blockIdx.y];
+  if (!c.period && ((reinterpret_cast<uintptr_t>(c.dst) | reinterpret_cast<uintptr_t>(c.src)) & 15u) == 0) {
+    // 16-byte accesses; the odd last unit, if any, by one thread
+    const uint64_t n128 = c.n64 >> 1;
+    uint4* d = reinterpret_cast<uint4*>(c.dst);
+    const uint4* s = reinterpret_cast<const uint4*>(c.src);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n128;
+         i += (uint64_t)gridDim.x * blockDim.x)
+      d[i] = s[i];
+    if ((c.n64 & 1) && blockIdx.x == 0 && threadIdx.x == 0) c.dst[c.n64 - 1] = c.src[c.n64 - 1];
+    return;
+  }
+  if (c.period) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < c.n64;
+         i += (uint64_t)gridDim.x * blockDim.x)
+      c.dst[i] = c.src[i % c.period];
+    return;
+  }
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < c.n64;
        i += (uint64_t)gridDim.x * blockDim.x)
     c.dst[i] = c.src[i];
@@ -64,12 +92,17 @@ hipError_t copy_many(const std::vector<CopyDesc>& v, hipStream_t s) {
   for (size_t off = 0; off < v.size(); off += kMaxCopies) {
     CopyList l;
     l.n = (uint32_t)std::min<size_t>(kMaxCopies, v.size() - off);
-    uint64_t mx = 0;
+    uint64_t mx = 0, units = 0;
     for (uint32_t i = 0; i < l.n; ++i) {
       l.d[i] = v[off + i];
       mx = std::max(mx, l.d[i].n64);
+      units += l.d[i].n64;
     }
-    const uint32_t bx = (uint32_t)std::min<uint64_t>(256, (mx + 255) / 256);
+    // blocks per descriptor: one per 512 units of the longest, at most 16384
+    // blocks in all (at least 64 per descriptor); the loops stride the rest
+    const uint64_t cap = std::max<uint64_t>(64, 16384 / l.n);
+    const uint32_t bx = (uint32_t)std::min<uint64_t>(cap, (mx + 511) / 512);
+    LaunchTimer t("server_copy", "u64", 0, false, false, units, s);
     hipLaunchKernelGGL(copy_list_kernel, dim3(std::max(1u, bx), l.n), dim3(256), 0, s, l);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -81,6 +114,7 @@ struct Req {
   uint64_t id = 0;
   ntt_request r{};
   std::vector<uint64_t> moduli;
+  int cls = -1;         // arithmetic class shared by every modulus, or -1
   uint64_t words = 0;   // batch * L * N
   uint64_t bytes = 0;   // device bytes held while in flight
   ntt_request_info info{};
@@ -100,6 +134,20 @@ using ShapeKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, std::vector<
 
 ShapeKey shape_of(const Req* q) {
   return ShapeKey(q->r.op, q->r.N, q->r.word_bits, q->r.memory, q->moduli);
+}
+
+// Requests of different moduli share a launch when this key matches and is
+// defined (cls >= 0).
+using MergeKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t, int>;
+MergeKey merge_of(const Req* q) {
+  return MergeKey(q->r.op, q->r.N, q->r.word_bits, q->r.memory, q->cls);
+}
+
+// Arithmetic class of one modulus (the plan's rule): 32-bit words, fp64 with
+// 64-bit words below kF64LBound, 64-bit integer above.
+int class_of(uint64_t q, uint32_t word_bits) {
+  if (word_bits == 32) return 0;
+  return q < kF64LBound ? 1 : 2;
 }
 
 }  // namespace
@@ -123,6 +171,12 @@ struct ntt_server_s {
   uint32_t max_reqs = 64;  // requests per launch
   std::map<std::tuple<uint32_t, uint32_t, std::vector<uint64_t>>, ntt_plan_t> plans;
 
+  // Moduli already checked for (N, word_bits): a submit checks each modulus of
+  // a request once per server, not once per request (a check costs a few
+  // microseconds; a request carries up to dozens of moduli).
+  std::mutex checked_mu;
+  std::set<std::tuple<uint32_t, uint32_t, uint64_t>> checked;
+
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> pending;
@@ -134,8 +188,11 @@ struct ntt_server_s {
   ntt_server_counters ctr{};
   std::thread th;
 
+  uint32_t* d_iota = nullptr;  // 0, 1, ..., kMaxMergedLimbs - 1: the limb list of a merged launch
+
   bool serial() const { return flags & NTT_SERVER_SERIAL; }
   bool dry() const { return flags & NTT_SERVER_DRY_RUN; }
+  bool merging() const { return !serial() && (flags & NTT_SERVER_MERGE_MODULI); }
 
   ntt_plan_t plan_for(const Req* q, ntt_status* st) {
     auto key = std::make_tuple(q->r.N, q->r.word_bits, q->moduli);
@@ -172,10 +229,46 @@ struct ntt_server_s {
     ntt_plan_t plan = plan_for(q0, &st);
     if (!plan) return st;
     const uint32_t wb = q0->r.word_bits / 8;
-    const uint64_t per = (uint64_t)q0->moduli.size() * q0->r.N;  // words per polynomial
     const bool pm = q0->r.op == NTT_REQ_POLYMUL;
     const bool host = q0->r.memory == NTT_REQ_HOST;
     const bool single = b->reqs.size() == 1 && !host;
+    bool mixed = false;
+    for (const Req* q : b->reqs) mixed = mixed || q->moduli != q0->moduli;
+    // A launch over requests of different moduli runs one polynomial of a
+    // virtual plan whose limbs are every request's limbs, polynomial by
+    // polynomial, in gather order.  Its host constants are concatenated here;
+    // its device constants are gathered into the arena with the operands.
+    ntt_plan_s vp;
+    std::vector<const ntt_plan_s*> src_plans;
+    ntt_plan_t run = plan;
+    uint32_t run_batch = polys;
+    if (mixed) {
+      if (!d_iota) return fail(NTT_ENOMEM, "server limb list missing");
+      vp.device = plan->device;
+      vp.N = plan->N;
+      vp.log_n = plan->log_n;
+      vp.word_bits = plan->word_bits;
+      vp.log_n1 = plan->log_n1;
+      for (const Req* q : b->reqs) {
+        ntt_plan_t qp = plan_for(q, &st);
+        if (!qp) return st;
+        src_plans.push_back(qp);
+        for (uint32_t k = 0; k < q->r.batch; ++k) {
+          vp.moduli.insert(vp.moduli.end(), qp->moduli.begin(), qp->moduli.end());
+          vp.psi.insert(vp.psi.end(), qp->psi.begin(), qp->psi.end());
+          vp.cls.insert(vp.cls.end(), qp->cls.begin(), qp->cls.end());
+          vp.h_limbs.insert(vp.h_limbs.end(), qp->h_limbs.begin(), qp->h_limbs.end());
+        }
+      }
+      vp.L = (uint32_t)vp.moduli.size();
+      const int c = q0->cls;
+      vp.cls_cnt[c] = vp.L;
+      vp.h_cls_limbs.resize(vp.L);
+      for (uint32_t l = 0; l < vp.L; ++l) vp.h_cls_limbs[l] = l;
+      vp.d_cls_limbs = d_iota;
+      run = &vp;
+      run_batch = 1;
+    }
     hipError_t e = hipSuccess;
     // Grow this stream's arena to `need` bytes: wait for its earlier batches,
     // then reallocate (rare: the arena keeps its largest size).  The arenas
@@ -227,16 +320,33 @@ struct ntt_server_s {
       }
     } else {
       // Gather every operand into one contiguous batch, run one launch, scatter.
-      // Arena layout: A | B | O | polymul workspace (polymul), A (transforms).
-      const uint64_t total = (uint64_t)polys * per * wb;
-      const size_t ws = pm ? polymul_ws_bytes(plan, polys) : 0;
-      const size_t need = (size_t)total * (pm ? 3 : 1) + ws;
+      // Arena layout: A | B | O | polymul workspace (polymul), A (transforms);
+      // then, for a mixed launch, the virtual plan's limb constants.
+      uint64_t total = 0;
+      for (const Req* q : b->reqs) total += q->words * wb;
+      const size_t ws = pm ? polymul_ws_bytes(run, run_batch) : 0;
+      const size_t limb_off = (((size_t)total * (pm ? 3 : 1) + ws) + 255) & ~(size_t)255;
+      const size_t need = mixed ? limb_off + (size_t)vp.L * sizeof(LimbDev)
+                                : (size_t)total * (pm ? 3 : 1) + ws;
       if ((e = reserve(need)) != hipSuccess) return hip_fail(e, "server staging allocation");
       void* A = arena[b->stream];
       void* B = pm ? static_cast<unsigned char*>(A) + total : nullptr;
       void* O = pm ? static_cast<unsigned char*>(A) + 2 * total : nullptr;
       void* WS = ws ? static_cast<unsigned char*>(A) + 3 * total : nullptr;
       std::vector<CopyDesc> in;
+      if (mixed) {
+        static_assert(sizeof(LimbDev) % 8 == 0, "limb constants copy in 8-byte units");
+        unsigned char* dl = static_cast<unsigned char*>(A) + limb_off;
+        vp.d_limbs = reinterpret_cast<LimbDev*>(dl);
+        for (size_t i = 0; i < b->reqs.size(); ++i) {
+          const Req* q = b->reqs[i];
+          const uint64_t unit = q->moduli.size() * sizeof(LimbDev) / 8;
+          in.push_back(CopyDesc{reinterpret_cast<uint64_t*>(dl),
+                                reinterpret_cast<const uint64_t*>(src_plans[i]->d_limbs),
+                                unit * q->r.batch, unit});
+          dl += unit * 8 * q->r.batch;
+        }
+      }
       uint64_t off = 0;
       for (Req* q : b->reqs) {
         const uint64_t bytes = q->words * wb;
@@ -248,17 +358,18 @@ struct ntt_server_s {
                                hipMemcpyHostToDevice, s);
           if (e != hipSuccess) return hip_fail(e, "server input copy");
         } else {
-          in.push_back(CopyDesc{reinterpret_cast<uint64_t*>(da), static_cast<const uint64_t*>(q->r.a), bytes / 8});
+          in.push_back(CopyDesc{reinterpret_cast<uint64_t*>(da), static_cast<const uint64_t*>(q->r.a), bytes / 8, 0});
           if (pm)
             in.push_back(CopyDesc{reinterpret_cast<uint64_t*>(static_cast<unsigned char*>(B) + off),
-                                  static_cast<const uint64_t*>(q->r.b), bytes / 8});
+                                  static_cast<const uint64_t*>(q->r.b), bytes / 8, 0});
         }
         off += bytes;
       }
       if (!in.empty() && (e = copy_many(in, s)) != hipSuccess) return hip_fail(e, "server gather");
       void* res = pm ? O : A;
-      if (pm) st = polymul_into(plan, O, A, B, polys, WS, s);
-      else st = q0->r.op == NTT_REQ_FORWARD ? ntt_forward(plan, A, polys, s) : ntt_inverse(plan, A, polys, s);
+      if (pm) st = polymul_into(run, O, A, B, run_batch, WS, s);
+      else st = q0->r.op == NTT_REQ_FORWARD ? ntt_forward(run, A, run_batch, s)
+                                             : ntt_inverse(run, A, run_batch, s);
       if (st != NTT_OK) return st;
       std::vector<CopyDesc> outc;
       off = 0;
@@ -269,7 +380,7 @@ struct ntt_server_s {
           e = hipMemcpyAsync(q->r.out, src, bytes, hipMemcpyDeviceToHost, s);
           if (e != hipSuccess) return hip_fail(e, "server output copy");
         } else {
-          outc.push_back(CopyDesc{static_cast<uint64_t*>(q->r.out), reinterpret_cast<const uint64_t*>(src), bytes / 8});
+          outc.push_back(CopyDesc{static_cast<uint64_t*>(q->r.out), reinterpret_cast<const uint64_t*>(src), bytes / 8, 0});
         }
         off += bytes;
       }
@@ -332,25 +443,38 @@ struct ntt_server_s {
       b->bytes = head->bytes;
       uint32_t polys = head->r.batch;
       uint64_t words = head->words;
+      uint64_t limbs = (uint64_t)head->r.batch * head->moduli.size();
+      bool mixed = false;
       if (!serial()) {
         const ShapeKey key = shape_of(head);
+        const MergeKey mkey = merge_of(head);
+        const bool can_merge = merging() && head->cls >= 0;
         for (auto jt = pending.begin(); jt != pending.end();) {
           Req* q = *jt;
           if (b->reqs.size() >= max_reqs) break;
+          const uint64_t ql = (uint64_t)q->r.batch * q->moduli.size();
           // a launch covers fewer than 2^32 words (the library's per-call
           // limit), so a request never fails because of its batch mates
-          if (polys + q->r.batch <= max_batch && words + q->words < kMaxLaunchWords &&
-              inflight_bytes + b->bytes + q->bytes <= budget && shape_of(q) == key) {
+          const bool fits = polys + q->r.batch <= max_batch && words + q->words < kMaxLaunchWords &&
+                            inflight_bytes + b->bytes + q->bytes <= budget;
+          const bool same = fits && shape_of(q) == key;
+          const bool other = fits && !same && can_merge && q->cls >= 0 && merge_of(q) == mkey;
+          // a launch that mixes moduli holds at most kMaxMergedLimbs limb-rows
+          const bool mate = (same || other) && (!(mixed || other) || limbs + ql <= kMaxMergedLimbs);
+          if (mate) {
             b->reqs.push_back(q);
             b->bytes += q->bytes;
             polys += q->r.batch;
             words += q->words;
+            limbs += ql;
+            mixed = mixed || !same;
             jt = pending.erase(jt);
           } else {
             ++jt;
           }
         }
       }
+      if (mixed) ctr.merged_launches += 1;
       const double t = now_s();
       for (Req* q : b->reqs) q->info.t_admit = t;
       b->stream = pick_stream();
@@ -453,8 +577,16 @@ ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t 
       e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
       if (e == hipSuccess) s->streams.push_back(st);
     }
+    if (e == hipSuccess) {
+      std::vector<uint32_t> iota(kMaxMergedLimbs);
+      for (uint32_t i = 0; i < kMaxMergedLimbs; ++i) iota[i] = i;
+      e = hipMalloc(&s->d_iota, kMaxMergedLimbs * sizeof(uint32_t));
+      if (e == hipSuccess)
+        e = hipMemcpy(s->d_iota, iota.data(), kMaxMergedLimbs * sizeof(uint32_t), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
       for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+      if (s->d_iota) (void)hipFree(s->d_iota);
       delete s;
       return hip_fail(e, "server streams");
     }
@@ -478,14 +610,24 @@ ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id)
   if (!s->dry() && (!r->a || !r->out || (r->op == NTT_REQ_POLYMUL && !r->b)))
     return fail(NTT_EINVAL, "null operand");
   for (uint32_t l = 0; l < r->num_moduli; ++l) {
+    const auto key = std::make_tuple(r->N, r->word_bits, r->moduli[l]);
+    {
+      std::lock_guard<std::mutex> lk(s->checked_mu);
+      if (s->checked.count(key)) continue;
+    }
     const ntt_status st = ntt_check_modulus(r->N, r->moduli[l], r->word_bits);
     if (st != NTT_OK) return st;
+    std::lock_guard<std::mutex> lk(s->checked_mu);
+    s->checked.insert(key);
   }
   Req* q = new (std::nothrow) Req();
   if (!q) return fail(NTT_ENOMEM, "host allocation");
   q->r = *r;
   q->moduli.assign(r->moduli, r->moduli + r->num_moduli);
   q->r.moduli = nullptr;
+  q->cls = class_of(q->moduli[0], r->word_bits);
+  for (uint64_t m : q->moduli)
+    if (class_of(m, r->word_bits) != q->cls) q->cls = -1;
   q->words = (uint64_t)r->batch * r->num_moduli * r->N;
   if (q->words >= kMaxLaunchWords) {
     delete q;
@@ -577,6 +719,7 @@ ntt_status ntt_server_destroy(ntt_server_t s) {
     if (a) (void)hipFree(a);
   for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
   for (auto& kv : s->plans) ntt_plan_destroy(kv.second);
+  if (s->d_iota) (void)hipFree(s->d_iota);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   delete s;
   return NTT_OK;

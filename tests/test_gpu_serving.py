@@ -59,9 +59,11 @@ def _run(reqs, flags, streams=4, budget=8 << 30, memory=ntt.REQ_DEVICE):
         ptr_list.append((da.data_ptr(), db.data_ptr(), out.data_ptr()))
     torch.cuda.synchronize()
     with ntt.Server(budget, streams, 0, flags) as srv:
-        # all buffers exist before the first submit: the requests arrive as a burst
-        ids = [srv.submit(op, N, mods, wb, pairs, *ptrs, memory=memory)
-               for (op, N, mods, wb, pairs, a, b), ptrs in zip(reqs, ptr_list)]
+        # all buffers exist before the first submit, and the native load generator
+        # submits every request at t = 0: the requests arrive as a burst
+        batch = [(op, N, mods, wb, pairs, *ptrs, memory)
+                 for (op, N, mods, wb, pairs, a, b), ptrs in zip(reqs, ptr_list)]
+        ids = srv.replay(batch, [0.0] * len(batch))
         infos = [srv.wait(i, 120000) for i in ids]
         counters = srv.counters()
     torch.cuda.synchronize()
@@ -95,11 +97,12 @@ def test_host_memory_requests_and_a_small_budget():
     assert c["max_inflight_bytes"] <= big + (1 << 20)
 
 
-def test_serving_mix_at_full_size():
+@pytest.mark.parametrize("flags", [0, ntt.SERVER_MERGE_MODULI])
+def test_serving_mix_at_full_size(flags):
     """The serving configuration itself: 70% 1..64 polymul pairs at 2^10 over the
     32-bit prime, 30% one pair at 2^16 over 8..36 of the 50-bit primes, each with
-    its own inputs; continuous batching on 4 streams against the serial server
-    and the oracle, word for word."""
+    its own inputs; continuous batching on 4 streams (identical moduli only, and
+    merging moduli) against the serial server and the oracle, word for word."""
     reqs = []
     for i, r in enumerate(synth.c5_requests(7, 40, 1000.0)):
         a = synth.uniform_poly(r.seed, r.moduli, r.pairs, r.N)
@@ -107,10 +110,53 @@ def test_serving_mix_at_full_size():
         reqs.append((ntt.REQ_POLYMUL, r.N, r.moduli, r.word_bits, r.pairs, a, b))
     assert any(q[1] == 1 << 16 and len(q[2]) >= 30 for q in reqs)
     assert any(q[1] == 1 << 10 and q[4] >= 40 for q in reqs)
-    mixed, infos, c = _run(reqs, 0, streams=4, budget=64 << 30)
+    mixed, infos, c = _run(reqs, flags, streams=4, budget=64 << 30)
     alone, _, _ = _run(reqs, ntt.SERVER_SERIAL, streams=1, budget=64 << 30)
     assert max(x["batched_with"] for x in infos) > 1, "the mix should have batched something"
     for req, m, s in zip(reqs, mixed, alone):
         w = oracle.polymul(req[5], req[6], req[2])
+        assert np.array_equal(m, w)
+        assert np.array_equal(s, w)
+
+
+def _mixed_moduli_requests(seed):
+    """Requests whose moduli differ but share a class: 50-bit primes at N = 2^12
+    (on-chip polymul) and 2^14 (two-pass polymul with workspace), 32-bit primes
+    at N = 2^10, with 1..5 limbs, 1..3 polynomials, polymul / forward / inverse;
+    plus requests whose two moduli fall in two classes."""
+    p50 = synth.c2_primes(5)
+    p32 = synth.primes_below(1 << 32, 1 << 17, 4)
+    wide = [p50[0], synth.primes_below(1 << 61, 1 << 17, 1)[0]]
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(36):
+        kind = i % 6
+        if kind == 5:
+            N, mods, wb = 1 << 12, wide, 64
+        elif kind == 4:
+            N, mods, wb = 1 << 10, p32[: 1 + i % 4], 32
+        else:
+            N, mods, wb = (1 << 12) if kind < 2 else (1 << 14), p50[: 1 + int(rng.integers(0, 5))], 64
+        pairs = 1 + int(rng.integers(0, 3))
+        op = [ntt.REQ_POLYMUL, ntt.REQ_FORWARD, ntt.REQ_INVERSE][(i // 6) % 3]
+        a = synth.uniform_poly(seed * 1000 + 2 * i, mods, pairs, N)
+        b = synth.uniform_poly(seed * 1000 + 2 * i + 1, mods, pairs, N)
+        out.append((op, N, mods, wb, pairs, a, b))
+    return out
+
+
+@pytest.mark.parametrize("memory", [ntt.REQ_DEVICE, ntt.REQ_HOST])
+def test_requests_of_different_moduli_share_launches_word_for_word(memory):
+    """With NTT_SERVER_MERGE_MODULI, a launch over requests of different moduli
+    (one virtual plan over their limbs laid end to end) gives every request the
+    oracle's words and the words of the default server, which batches identical
+    moduli only."""
+    reqs = _mixed_moduli_requests(3)
+    merged, infos, c = _run(reqs, ntt.SERVER_MERGE_MODULI, streams=1, memory=memory)
+    same, _, c_same = _run(reqs, 0, streams=1, memory=memory)
+    assert c["merged_launches"] >= 1 and c_same["merged_launches"] == 0
+    assert c["launches"] < c_same["launches"]
+    for req, m, s in zip(reqs, merged, same):
+        w = _want(req)
         assert np.array_equal(m, w)
         assert np.array_equal(s, w)

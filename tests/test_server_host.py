@@ -53,26 +53,91 @@ def test_bad_requests_are_rejected():
             srv.submit(7, 1 << 10, [Q_SMALL], 32, 1)                       # bad op
 
 
-def test_same_shape_requests_share_launches_and_shapes_never_mix():
-    with ntt.Server(1 << 32, n_streams=1, max_batch=4096, flags=ntt.SERVER_DRY_RUN) as srv:
-        shapes = {}
-        ids = []
-        for i in range(200):
-            if i % 10 == 0:
-                rid = _big(srv, 8 + (i // 10) % 2)           # two different big shapes
-                shapes[rid] = ("big", 8 + (i // 10) % 2)
-            else:
-                rid = _small(srv, 1 + i % 7)
-                shapes[rid] = ("small", 0)
-            ids.append(rid)
-        infos = {i: srv.wait(i, 10000) for i in ids}
-        c = srv.counters()
-    assert c["launches"] < 200
-    assert max(x["batched_with"] for x in infos.values()) > 1
+def _two_big_shapes_and_small(srv):
+    shapes, ids = {}, []
+    for i in range(200):
+        if i % 10 == 0:
+            rid = _big(srv, 8 + (i // 10) % 2)           # two different big shapes
+            shapes[rid] = ("big", 8 + (i // 10) % 2)
+        else:
+            rid = _small(srv, 1 + i % 7)
+            shapes[rid] = ("small", 0)
+        ids.append(rid)
+    return shapes, {i: srv.wait(i, 10000) for i in ids}
+
+
+def _shapes_per_launch(shapes, infos):
     by_launch = {}
     for rid, x in infos.items():
         by_launch.setdefault(x["launch_id"], set()).add(shapes[rid])
+    return by_launch
+
+
+def test_same_shape_requests_share_launches_and_shapes_never_mix():
+    with ntt.Server(1 << 32, n_streams=1, max_batch=4096, flags=ntt.SERVER_DRY_RUN) as srv:
+        shapes, infos = _two_big_shapes_and_small(srv)
+        c = srv.counters()
+    assert c["launches"] < 200 and c["merged_launches"] == 0
+    assert max(x["batched_with"] for x in infos.values()) > 1
+    assert all(len(s) == 1 for s in _shapes_per_launch(shapes, infos).values())
+
+
+def test_requests_of_different_moduli_in_one_class_share_launches():
+    """With NTT_SERVER_MERGE_MODULI, big requests of 8 and of 9 limbs (same op, N,
+    width and class) may share a launch; big and small requests (other N, other
+    width) never do."""
+    with ntt.Server(1 << 32, n_streams=1, max_batch=4096,
+                    flags=ntt.SERVER_DRY_RUN | ntt.SERVER_MERGE_MODULI) as srv:
+        shapes, infos = _two_big_shapes_and_small(srv)
+        c = srv.counters()
+    by_launch = _shapes_per_launch(shapes, infos)
+    assert c["merged_launches"] >= 1
+    assert any(s == {("big", 8), ("big", 9)} for s in by_launch.values())
+    assert all(len({k for k, _ in s}) == 1 for s in by_launch.values())
+
+
+def test_moduli_spanning_classes_only_batch_with_identical_moduli():
+    """A request whose moduli fall in two arithmetic classes (one below 2^50,
+    one above) runs only beside requests of exactly its moduli."""
+    wide = synth.primes_below(1 << 61, 1 << 17, 2)
+    mixed_cls = [Q_BIG[0], wide[0]]
+    with ntt.Server(1 << 32, n_streams=1, flags=ntt.SERVER_DRY_RUN | ntt.SERVER_MERGE_MODULI) as srv:
+        kinds, ids = {}, []
+        for i in range(60):
+            if i % 3 == 0:
+                rid = srv.submit(ntt.REQ_POLYMUL, 1 << 16, mixed_cls, 64, 1)
+                kinds[rid] = "two-class"
+            else:
+                L = 2 + i % 2
+                rid = srv.submit(ntt.REQ_POLYMUL, 1 << 16, Q_BIG[:L], 64, 1)
+                kinds[rid] = "fp64"
+            ids.append(rid)
+        infos = {i: srv.wait(i, 10000) for i in ids}
+    by_launch = {}
+    for rid, x in infos.items():
+        by_launch.setdefault(x["launch_id"], set()).add(kinds[rid])
     assert all(len(s) == 1 for s in by_launch.values())
+    assert any(x["batched_with"] > 1 for rid, x in infos.items() if kinds[rid] == "two-class")
+
+
+def test_a_launch_of_different_moduli_holds_at_most_4096_limb_rows():
+    """Requests of 9 limbs x 100 polynomials and of 8 limbs x 100 polynomials:
+    a launch that mixes them stays within 4096 limb-rows."""
+    with ntt.Server(1 << 40, n_streams=1, flags=ntt.SERVER_DRY_RUN | ntt.SERVER_MERGE_MODULI) as srv:
+        limbs, ids = {}, []
+        for i in range(40):
+            L = 8 + i % 2
+            rid = srv.submit(ntt.REQ_FORWARD, 1 << 10, Q_BIG[:L], 64, 100)
+            limbs[rid] = (L, 100 * L)
+            ids.append(rid)
+        infos = {i: srv.wait(i, 10000) for i in ids}
+        c = srv.counters()
+    rows, kinds = {}, {}
+    for rid, x in infos.items():
+        rows[x["launch_id"]] = rows.get(x["launch_id"], 0) + limbs[rid][1]
+        kinds.setdefault(x["launch_id"], set()).add(limbs[rid][0])
+    assert c["merged_launches"] >= 1
+    assert all(rows[k] <= 4096 for k in rows if len(kinds[k]) > 1)
 
 
 def test_max_batch_caps_polynomials_per_launch():
