@@ -510,9 +510,11 @@ ntt_status ntt_server_destroy(ntt_server_t s);
  * batch * L) and no forced split use it.  The paper's switch trigger (chunks
  * closest to the SM count, Sec. V-D) is for one polynomial; a batch changes the
  * concurrency, so the split is measured per (N, class, rows).  Each split is
- * timed with 16 and with 8 values per row-pass thread and the faster is kept
- * per direction; polymul rows at the chosen split are timed the same way when
- * a second scratch buffer of the same size can be allocated. */
+ * timed with 16, 8 and 4 values per row-pass thread (where built) and the
+ * fastest is kept per direction; at the chosen split, column passes of 256, 128
+ * and 64 columns (threads) per workgroup are timed and the fastest kept;
+ * polymul rows at the chosen split are timed with 16 and 8 values per thread
+ * when a second scratch buffer of the same size can be allocated. */
 ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_moduli,
                           uint32_t word_bits, uint32_t batch, uint32_t* best_n1, float* best_us);
 

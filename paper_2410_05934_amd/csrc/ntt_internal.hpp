@@ -33,6 +33,7 @@ struct ntt_plan_s {
   uint32_t log_n1 = 0;                // default column stages (0: single pass)
   int forced_split = -1;              // NTT_FLAG_SPLIT, or -1
   int row_rb = 0;                     // forced log2 values per thread in row passes (0: choose)
+  uint32_t col_block = 0;             // forced column-pass workgroup size (0: choose)
   std::vector<uint64_t> moduli, psi;
   std::vector<uint32_t> cls;          // arithmetic class per limb
   nttk::LimbDev* d_limbs = nullptr;   // device [L]
@@ -140,6 +141,16 @@ inline int row_rb_for(const ntt_plan_s* p, bool inv, uint32_t split, uint32_t ba
   const int rb = (int)tuned_row_rb(inv ? 3u : 2u, p->log_n, (uint32_t)cls, (uint64_t)batch * p->L,
                                    fallback);
   return row_rb_ok(rb, n2) ? rb : 4;
+}
+
+// Columns (threads) per workgroup of column passes: forced by the plan (the
+// tuner's measurements), else the tuning table, else 256.  One thread per column,
+// so this is both the waves per workgroup (1, 2, 4) and the transforms' columns
+// a workgroup holds.
+uint32_t tuned_col_block(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback);
+inline uint32_t col_block_for(const ntt_plan_s* p, uint32_t batch) {
+  if (p->col_block) return p->col_block;
+  return tuned_col_block(p->log_n, (uint32_t)dominant_class(p), (uint64_t)batch * p->L, 256u);
 }
 
 inline int polymul_rb_for(const ntt_plan_s* p, uint32_t split, uint32_t batch) {

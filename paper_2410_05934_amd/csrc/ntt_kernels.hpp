@@ -79,6 +79,7 @@ struct ColArgs {
   const void* src2;          //   threads total_cols .. 2*total_cols-1 take it
   uint32_t limb0;            // n_cls == 1: the limb and its constants (as in RowArgs)
   LimbDev one;
+  uint32_t block;            // launch: threads (columns) per workgroup, 64..kColBlock
 };
 
 struct EltArgs {
@@ -707,7 +708,8 @@ polymul_row_kernel(RowArgs args) {
 }
 
 // ---------------------------------------------------------------------------
-// Column pass: one thread owns one column of N1 = 2^LOGN1 elements.
+// Column pass: one thread owns one column of N1 = 2^LOGN1 elements; a
+// workgroup holds 64, 128 or kColBlock columns (the launch chooses).
 constexpr int kColBlock = 256;
 
 // One column of N1 = 2^LOGN1 words at src[k << log_n2], k < N1, written to the
@@ -793,7 +795,7 @@ template <class A, int LOGN1, bool INV, bool TWO_PASS, bool ONE = false>
 __global__ void __launch_bounds__(kColBlock)
 col_kernel(ColArgs args) {
   using W = typename A::W;
-  uint32_t gid = blockIdx.x * kColBlock + threadIdx.x;
+  uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   void* dst_base = args.dst;
   const void* src_base = args.src;
   if (args.src2 && gid >= args.total_cols) {

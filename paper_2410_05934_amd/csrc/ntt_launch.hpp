@@ -49,12 +49,13 @@ hipError_t launch_fm_n(const RowArgs& a, hipStream_t s) {
 template <class A, int LOGN1, bool INV, bool TWO>
 hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
   const uint64_t threads = (uint64_t)a.total_cols * (a.src2 ? 2 : 1);
-  const uint32_t blocks = (uint32_t)((threads + kColBlock - 1) / kColBlock);
+  const uint32_t bs = (a.block == 64 || a.block == 128) ? a.block : (uint32_t)kColBlock;
+  const uint32_t blocks = (uint32_t)((threads + bs - 1) / bs);
   LaunchTimer t("col", A::kName, LOGN1, INV, TWO, threads << LOGN1, s);
   if (a.n_cls == 1)
-    hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO, true>), dim3(blocks), dim3(kColBlock), 0, s, a);
+    hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO, true>), dim3(blocks), dim3(bs), 0, s, a);
   else
-    hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(kColBlock), 0, s, a);
+    hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO>), dim3(blocks), dim3(bs), 0, s, a);
   return hipGetLastError();
 }
 
@@ -171,6 +172,7 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.src2 = nullptr;
   a.limb0 = p->cls_cnt[c] == 1 ? p->h_cls_limbs[p->cls_off[c]] : 0u;
   a.one = p->h_limbs[a.limb0];
+  a.block = col_block_for(p, batch);
   return a;
 }
 

@@ -7,10 +7,15 @@
 // batch * L * N1 chunks and the best split moves with the batch.  The tuner
 // therefore measures: for a shape it times every admissible split on scratch
 // data and records the fastest under the key (log2 N, arithmetic class,
-// floor(log2(batch * L))).  With each split it also times both row-pass
-// radices (16 or 8 values per thread) per direction and records the faster.
-// Calls without a forced split look the keys up (the nearest recorded row
-// bucket within two powers of two), else use the defaults.
+// floor(log2(batch * L))).  With each split it also times the row-pass radices
+// (16, 8 or 4 values per thread: the threads per chunk, the paper's threads per
+// block) per direction and records the fastest; at the chosen split and radices
+// it times column passes of 256, 128 and 64 columns per workgroup (4, 2 or 1
+// waves; one thread per column), then polymul rows of both radices.  Calls
+// without a forced split look the keys up (the nearest recorded row bucket
+// within two powers of two), else use the defaults.  The row pass's LDS padding
+// is fixed (one spare slot per 16 words): its bank conflicts are measured at
+// 0.04-0.12 per access, so there is nothing for a search to win.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +41,8 @@ struct Entry {
 };
 
 // key: (kind, log_n, cls, bucket); kind 0 = pass split, 1 = ragged row length,
-// 2 / 3 / 4 = values per thread (log2) of forward / inverse / polymul row passes
+// 2 / 3 / 4 = values per thread (log2) of forward / inverse / polymul row passes,
+// 5 = columns (threads) per workgroup of the column passes
 using Key = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
 
 std::mutex g_mu;
@@ -104,24 +110,11 @@ __global__ void fill_words(uint64_t* p, size_t n64) {
 
 }  // namespace
 
-uint32_t tuned_split_for(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  ensure_env_loaded();
-  const uint32_t b = bucket_of(rows);
-  for (int d = 0; d <= 2; ++d) {
-    for (int sgn : {1, -1}) {
-      const int bb = (int)b + sgn * d;
-      if (bb < 0) continue;
-      auto it = g_table.find(Key(0u, log_n, cls, (uint32_t)bb));
-      if (it != g_table.end() && split_valid((int)log_n, (int)it->second.value))
-        return it->second.value;
-      if (d == 0) break;
-    }
-  }
-  return fallback;
-}
-
-uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback) {
+namespace {
+// The entry of `kind` for (log_n, cls) recorded at the bucket of `rows`, else at
+// the nearest bucket within two powers of two whose value `ok` accepts.
+template <class Ok>
+uint32_t lookup(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback, Ok ok) {
   std::lock_guard<std::mutex> lk(g_mu);
   ensure_env_loaded();
   const uint32_t b = bucket_of(rows);
@@ -130,12 +123,26 @@ uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows
       const int bb = (int)b + sgn * d;
       if (bb < 0) continue;
       auto it = g_table.find(Key(kind, log_n, cls, (uint32_t)bb));
-      if (it != g_table.end() && it->second.value >= 2 && it->second.value <= 4)
-        return it->second.value;
+      if (it != g_table.end() && ok(it->second.value)) return it->second.value;
       if (d == 0) break;
     }
   }
   return fallback;
+}
+}  // namespace
+
+uint32_t tuned_split_for(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback) {
+  return lookup(0u, log_n, cls, rows, fallback,
+                [&](uint32_t v) { return split_valid((int)log_n, (int)v); });
+}
+
+uint32_t tuned_row_rb(uint32_t kind, uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback) {
+  return lookup(kind, log_n, cls, rows, fallback, [](uint32_t v) { return v >= 2 && v <= 4; });
+}
+
+uint32_t tuned_col_block(uint32_t log_n, uint32_t cls, uint64_t rows, uint32_t fallback) {
+  return lookup(5u, log_n, cls, rows, fallback,
+                [](uint32_t v) { return v == 64 || v == 128 || v == 256; });
 }
 
 uint32_t tuned_ragged_row_log(uint32_t log_n, uint32_t fallback) {
@@ -228,6 +235,31 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
     }
     any = true;
   }
+  // Column-pass workgroup size at the chosen split and radices (the default,
+  // 256, unless another is faster).
+  uint32_t best_cb = 0;
+  float best_cb_us = 0.f;
+  if (st == NTT_OK && any && best_split > 0) {
+    float bc = 1e30f;
+    for (uint32_t cb : {256u, 128u, 64u}) {
+      ntt_plan_t p = nullptr;
+      st = ntt_plan_create(&p, N, moduli, num_moduli, word_bits, NTT_FLAG_SPLIT(best_split));
+      if (st != NTT_OK) break;
+      p->col_block = cb;
+      float uf = 0, ui = 0;
+      p->row_rb = (int)best_rb_f;
+      st = time_dir(p, false, &uf);
+      p->row_rb = (int)best_rb_i;
+      if (st == NTT_OK) st = time_dir(p, true, &ui);
+      ntt_plan_destroy(p);
+      if (st != NTT_OK) break;
+      if (uf + ui < bc) {
+        bc = uf + ui;
+        best_cb = cb;
+      }
+    }
+    best_cb_us = bc;
+  }
   // Polymul rows at the chosen split: radix-16 against radix-8 (b aliases a; out
   // is a second buffer).  Skipped when that buffer cannot be had.
   uint32_t best_rb_pm = 0;
@@ -281,6 +313,7 @@ ntt_status ntt_tune_split(uint32_t N, const uint64_t* moduli, uint32_t num_modul
     g_table[Key(2u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_f, 0.f};
     g_table[Key(3u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_i, 0.f};
     if (best_rb_pm) g_table[Key(4u, (uint32_t)log_n, cls, bk)] = Entry{best_rb_pm, 0.f};
+    if (best_cb) g_table[Key(5u, (uint32_t)log_n, cls, bk)] = Entry{best_cb, best_cb_us};
   }
   if (best_n1) *best_n1 = best_split;
   if (best_us) *best_us = best;

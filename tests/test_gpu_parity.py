@@ -453,6 +453,43 @@ def test_tuning_table_radix16_rows_are_bit_identical(cls, logn, tmp_path):
 
 
 @pytest.mark.parametrize("cls", ["u32", "f64", "i64", "mixed64"])
+@pytest.mark.parametrize("logn", [5, 9, 12, 16])
+@pytest.mark.parametrize("block", [64, 128])
+def test_tuning_table_column_workgroup_sizes_are_bit_identical(cls, logn, block, tmp_path):
+    """A tuning table that picks 64 or 128 columns per column-pass workgroup gives
+    the oracle's words at every split, forward, inverse and polymul, with column
+    counts that leave the last workgroup partly empty (3 polynomials)."""
+    import json
+    word_bits, moduli = CLASSES[cls]
+    N = 1 << logn
+    entries = [{"kind": 5, "log_n": logn, "cls": c, "bucket": b, "value": block}
+               for c in range(3) for b in range(25)]
+    path = tmp_path / "cb.json"
+    path.write_text(json.dumps({"entries": entries}))
+    ntt.tune_clear()
+    ntt.tune_load(str(path))
+    try:
+        a = _data(95 + logn, moduli, 3, N, word_bits)
+        b = _data(96 + logn, moduli, 3, N, word_bits)
+        want_f = oracle.forward(a, moduli)
+        want_i = oracle.inverse(a, moduli)
+        for n1 in _valid_splits(logn):
+            if n1 == 0:
+                continue
+            plan = ntt.Plan(N, moduli, word_bits, flags=ntt.flag_split(n1))
+            assert np.array_equal(_run_fwd(plan, a, word_bits), want_f), n1
+            assert np.array_equal(_run_inv(plan, a, word_bits), want_i), n1
+        plan = ntt.Plan(N, moduli, word_bits)
+        da, db = to_device(a, word_bits), to_device(b, word_bits)
+        out = empty_device(a.shape, word_bits)
+        plan.polymul(out, da, db)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out, word_bits).astype(np.uint64), oracle.polymul(a, b, moduli))
+    finally:
+        ntt.tune_clear()
+
+
+@pytest.mark.parametrize("cls", ["u32", "f64", "i64", "mixed64"])
 @pytest.mark.parametrize("logn", [13, 14, 15, 16])
 @pytest.mark.parametrize("batch", [1, 3])
 def test_single_launch_two_pass_is_bit_identical(cls, logn, batch):

@@ -208,6 +208,11 @@ def test_tuner_records_and_uses_a_valid_split(tmp_path):
     assert np.array_equal(to_host(d, 64), oracle.forward(a, mods))
     path = str(tmp_path / "tune.json")
     ntt.tune_save(path)
+    import json
+    kinds = {e["kind"]: e["value"] for e in json.load(open(path))["entries"]}
+    assert kinds[0] == best and kinds[2] in (2, 3, 4) and kinds[3] in (2, 3, 4)
+    if best > 0:  # a column pass: its workgroup size was measured too
+        assert kinds[5] in (64, 128, 256)
     ntt.tune_clear()
     assert plan.split_for(4) == plan.split
     ntt.tune_load(path)
