@@ -449,6 +449,8 @@ typedef struct {
   uint64_t arena_bytes;         /* staging arenas held now (never above the budget) */
   uint64_t max_arena_bytes;     /* high-water mark of arena_bytes */
   uint64_t merged_launches;     /* launches whose requests had different moduli */
+  uint64_t direct_launches;     /* batched two-pass polymul launches that read and wrote the
+                                   requests' buffers in place (no gather or scatter copies) */
 } ntt_server_counters;
 
 typedef struct ntt_server_s* ntt_server_t;
@@ -469,11 +471,13 @@ typedef struct ntt_server_s* ntt_server_t;
  * them fall in one arithmetic class (at most 4096 limb-rows per such launch).
  * A submit checks each distinct modulus once per server.  Plans and their twiddle
  * tables stay resident for the server's life.  max_batch caps the polynomials
- * per launch (0 = 4096); a launch also takes at most 64 requests.  Batched
- * operands are staged in a per-stream device arena that grows on demand and
- * is reused in stream order; the arenas together stay within budget_bytes
- * (another stream's arena is released, after its stream has drained, when
- * growing one would pass it). */
+ * per launch (0 = 4096); a launch also takes at most 64 requests.  A batched
+ * polymul of device-resident requests whose transforms take two passes reads
+ * and writes the requests' buffers in place (row-address tables); other
+ * batched operands are staged in a per-stream device arena.  Arenas (also
+ * holding intermediates and workspaces) grow on demand and are reused in
+ * stream order; together they stay within budget_bytes (another stream's arena
+ * is released, after its stream has drained, when growing one would pass it). */
 ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t n_streams,
                              uint32_t max_batch, uint32_t flags);
 

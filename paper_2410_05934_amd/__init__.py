@@ -339,7 +339,7 @@ class _ServerCounters(ctypes.Structure):
     _fields_ = [(n, _u64) for n in ("submitted", "completed", "rejected", "launches",
                                     "max_inflight_bytes", "max_inflight_requests",
                                     "budget_bytes", "plans_cached", "arena_bytes",
-                                    "max_arena_bytes", "merged_launches")]
+                                    "max_arena_bytes", "merged_launches", "direct_launches")]
 
 
 class Server:

@@ -201,4 +201,14 @@ size_t polymul_ws_bytes(const ntt_plan_s* p, uint32_t batch);
 ntt_status polymul_into(const ntt_plan_s* p, void* out, const void* a, const void* b,
                         uint32_t batch, void* ws, hipStream_t s);
 
+// Polymul of `batch` polynomials whose limb-rows live anywhere: row
+// poly * L + limb of a, b and out is at a_rows / b_rows / out_rows[row] (device
+// arrays of byte addresses, batch * L each).  o and ws are two contiguous
+// scratch buffers of batch * L * N words.  Only for calls whose polymul split
+// has both passes (polymul_rows_ok); the words are those of polymul_into.
+bool polymul_rows_ok(const ntt_plan_s* p, uint32_t batch);
+ntt_status polymul_rows_into(const ntt_plan_s* p, const uint64_t* out_rows, const uint64_t* a_rows,
+                             const uint64_t* b_rows, uint32_t batch, void* o, void* ws,
+                             hipStream_t s);
+
 }  // namespace nttk

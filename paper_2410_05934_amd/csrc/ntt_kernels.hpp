@@ -80,6 +80,13 @@ struct ColArgs {
   uint32_t limb0;            // n_cls == 1: the limb and its constants (as in RowArgs)
   LimbDev one;
   uint32_t block;            // launch: threads (columns) per workgroup, 64..kColBlock
+  // Optional row tables (kernels built with ROWS): the byte address of limb-row
+  // poly * L + limb of src / src2 / dst, in place of base + row * N words; a
+  // null table means the contiguous layout.  Lets one launch read and write
+  // operands that live in separate buffers.
+  const uint64_t* src_rows;
+  const uint64_t* src2_rows;
+  const uint64_t* dst_rows;
 };
 
 struct EltArgs {
@@ -791,36 +798,48 @@ __device__ __forceinline__ void col_one(typename A::W* __restrict__ dst,
 
 // ONE: the launch's class holds one limb (n_cls == 1), whose index and constants
 // come from the arguments; its twiddles are then wave-uniform loads.
-template <class A, int LOGN1, bool INV, bool TWO_PASS, bool ONE = false>
+// ROWS: the launch may carry row tables (ColArgs::src_rows and the others).
+template <class A, int LOGN1, bool INV, bool TWO_PASS, bool ONE = false, bool ROWS = false>
 __global__ void __launch_bounds__(kColBlock)
 col_kernel(ColArgs args) {
   using W = typename A::W;
   uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   void* dst_base = args.dst;
   const void* src_base = args.src;
-  if (args.src2 && gid >= args.total_cols) {
+  const uint64_t* src_rows = ROWS ? args.src_rows : nullptr;
+  const uint64_t* dst_rows = ROWS ? args.dst_rows : nullptr;
+  if ((args.src2 || (ROWS && args.src2_rows)) && gid >= args.total_cols) {
     gid -= args.total_cols;
     dst_base = args.dst2;
     src_base = args.src2;
+    src_rows = ROWS ? args.src2_rows : nullptr;
+    dst_rows = nullptr;
   }
   const bool valid = gid < args.total_cols;
   const uint32_t g = valid ? gid : 0;
   const uint32_t n2 = 1u << args.log_n2;
   const uint32_t r = g & (n2 - 1);
   const uint32_t rest = g >> args.log_n2;
+  // the column's words in its limb-row (poly * L + limb) of src and dst
+  auto at = [&](uint64_t row, W** d, const W** sp) {
+    *d = reinterpret_cast<W*>(dst_base) + (row << args.log_n) + r;
+    *sp = reinterpret_cast<const W*>(src_base) + (row << args.log_n) + r;
+    if constexpr (ROWS) {
+      if (dst_rows) *d = reinterpret_cast<W*>(dst_rows[row]) + r;
+      if (src_rows) *sp = reinterpret_cast<const W*>(src_rows[row]) + r;
+    }
+  };
+  W* d;
+  const W* sp;
   if constexpr (ONE) {
-    const uint64_t off = (((uint64_t)rest * args.L + args.limb0) << args.log_n) + r;
-    col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(dst_base) + off,
-                                     reinterpret_cast<const W*>(src_base) + off, args.one,
-                                     args.log_n2, valid);
+    at((uint64_t)rest * args.L + args.limb0, &d, &sp);
+    col_one<A, LOGN1, INV, TWO_PASS>(d, sp, args.one, args.log_n2, valid);
   } else {
     const uint32_t li = rest % args.n_cls;
     const uint32_t poly = rest / args.n_cls;
     const uint32_t limb = args.cls_limbs[li];
-    const uint64_t off = (((uint64_t)poly * args.L + limb) << args.log_n) + r;
-    col_one<A, LOGN1, INV, TWO_PASS>(reinterpret_cast<W*>(dst_base) + off,
-                                     reinterpret_cast<const W*>(src_base) + off, args.limbs[limb],
-                                     args.log_n2, valid);
+    at((uint64_t)poly * args.L + limb, &d, &sp);
+    col_one<A, LOGN1, INV, TWO_PASS>(d, sp, args.limbs[limb], args.log_n2, valid);
   }
 }
 

@@ -48,10 +48,22 @@ hipError_t launch_fm_n(const RowArgs& a, hipStream_t s) {
 
 template <class A, int LOGN1, bool INV, bool TWO>
 hipError_t launch_col_n(const ColArgs& a, hipStream_t s) {
-  const uint64_t threads = (uint64_t)a.total_cols * (a.src2 ? 2 : 1);
+  const uint64_t threads = (uint64_t)a.total_cols * ((a.src2 || a.src2_rows) ? 2 : 1);
   const uint32_t bs = (a.block == 64 || a.block == 128) ? a.block : (uint32_t)kColBlock;
   const uint32_t blocks = (uint32_t)((threads + bs - 1) / bs);
   LaunchTimer t("col", A::kName, LOGN1, INV, TWO, threads << LOGN1, s);
+  if constexpr (TWO) {
+    // row tables: built for the two-pass column launches only
+    if (a.src_rows || a.src2_rows || a.dst_rows) {
+      if (a.n_cls == 1)
+        hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO, true, true>), dim3(blocks), dim3(bs), 0, s, a);
+      else
+        hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO, false, true>), dim3(blocks), dim3(bs), 0, s, a);
+      return hipGetLastError();
+    }
+  } else {
+    if (a.src_rows || a.src2_rows || a.dst_rows) return hipErrorInvalidValue;
+  }
   if (a.n_cls == 1)
     hipLaunchKernelGGL((col_kernel<A, LOGN1, INV, TWO, true>), dim3(blocks), dim3(bs), 0, s, a);
   else
@@ -173,6 +185,7 @@ inline ColArgs col_args(const ntt_plan_s* p, int c, void* dst, const void* src, 
   a.limb0 = p->cls_cnt[c] == 1 ? p->h_cls_limbs[p->cls_off[c]] : 0u;
   a.one = p->h_limbs[a.limb0];
   a.block = col_block_for(p, batch);
+  a.src_rows = a.src2_rows = a.dst_rows = nullptr;
   return a;
 }
 
@@ -357,6 +370,31 @@ hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, con
   RowArgs ra = row_args(p, c, out, out, ws, batch, n1);
   if ((e = launch_pm<A, true>(n2, ra, s, rb)) != hipSuccess) return e;
   ca = col_args(p, c, out, out, batch, n1);
+  return launch_col<A, true, true>(n1, ca, s);
+}
+
+// Two-pass polymul whose operands and results live in separate buffers: limb-row
+// poly * L + limb of a, b and out is at a_rows / b_rows / out_rows[that row]
+// (byte addresses).  The first column launch reads a and b through the tables
+// (into o and ws), the last one writes out through its table; o and ws are
+// contiguous [batch][L][N] scratch.  The caller checks polymul_rows_ok.
+template <class A>
+hipError_t polymul_rows_cls(const ntt_plan_s* p, int c, const uint64_t* out_rows,
+                            const uint64_t* a_rows, const uint64_t* b_rows, void* o, void* ws,
+                            uint32_t batch, uint32_t split, hipStream_t s) {
+  const int n = p->log_n, n1 = (int)split, n2 = n - n1;
+  if (n1 == 0 || n2 == 0) return hipErrorInvalidValue;
+  const int rb = polymul_rb_for(p, split, batch);
+  hipError_t e;
+  ColArgs ca = col_args(p, c, o, nullptr, batch, n1);
+  ca.src_rows = a_rows;
+  ca.dst2 = ws;
+  ca.src2_rows = b_rows;
+  if ((e = launch_col<A, false, true>(n1, ca, s)) != hipSuccess) return e;
+  RowArgs ra = row_args(p, c, o, o, ws, batch, n1);
+  if ((e = launch_pm<A, true>(n2, ra, s, rb)) != hipSuccess) return e;
+  ca = col_args(p, c, nullptr, o, batch, n1);
+  ca.dst_rows = out_rows;
   return launch_col<A, true, true>(n1, ca, s);
 }
 

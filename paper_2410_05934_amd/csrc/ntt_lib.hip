@@ -166,6 +166,10 @@ template <class A>
 hipError_t polymul_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* b,
                        void* ws, uint32_t batch, uint32_t split, hipStream_t s);
 template <class A>
+hipError_t polymul_rows_cls(const ntt_plan_s* p, int c, const uint64_t* out_rows,
+                            const uint64_t* a_rows, const uint64_t* b_rows, void* o, void* ws,
+                            uint32_t batch, uint32_t split, hipStream_t s);
+template <class A>
 hipError_t mac_cls(const ntt_plan_s* p, int c, void* out, const void* a, const void* key,
                    uint32_t rows, uint32_t cols, uint32_t num_operands, hipStream_t s);
 template <class A>
@@ -190,7 +194,10 @@ hipError_t xprod_cls(const ntt_plan_s* p, int c, void* out, const void* a, const
                                           uint32_t, uint32_t, uint32_t, const uint32_t*);
 #define NTT_EXTERN_FWDMUL(A)                                                             \
   extern template hipError_t fwdmul_cls<A>(const ntt_plan_s*, int, void*, void*, void*, uint32_t, \
-                                           uint32_t, hipStream_t);
+                                           uint32_t, hipStream_t);                              \
+  extern template hipError_t polymul_rows_cls<A>(const ntt_plan_s*, int, const uint64_t*,      \
+                                                 const uint64_t*, const uint64_t*, void*, void*, \
+                                                 uint32_t, uint32_t, hipStream_t);
 NTT_EXTERN_FWDMUL(ArF64S)
 NTT_EXTERN_FWDMUL(ArF64L)
 NTT_EXTERN_FWDMUL(ArI64)
@@ -394,6 +401,21 @@ ntt_status polymul_into(const ntt_plan_s* plan, void* out, const void* a, const 
   const uint32_t split = polymul_split(plan, call_split(plan, batch));
   if (split && !ws) return fail(NTT_EINVAL, "polymul workspace missing");
   NTT_FOR_CLASSES(plan, (polymul_cls<A>(plan, c, out, a, b, ws, batch, split, s)));
+  return NTT_OK;
+}
+
+bool polymul_rows_ok(const ntt_plan_s* p, uint32_t batch) {
+  const uint32_t split = polymul_split(p, call_split(p, batch));
+  return split > 0 && split < p->log_n;
+}
+
+ntt_status polymul_rows_into(const ntt_plan_s* plan, const uint64_t* out_rows, const uint64_t* a_rows,
+                             const uint64_t* b_rows, uint32_t batch, void* o, void* ws,
+                             hipStream_t s) {
+  if (!polymul_rows_ok(plan, batch)) return fail(NTT_EINVAL, "polymul through row tables needs two passes");
+  if (!o || !ws || !out_rows || !a_rows || !b_rows) return fail(NTT_EINVAL, "null argument");
+  const uint32_t split = polymul_split(plan, call_split(plan, batch));
+  NTT_FOR_CLASSES(plan, (polymul_rows_cls<A>(plan, c, out_rows, a_rows, b_rows, o, ws, batch, split, s)));
   return NTT_OK;
 }
 }  // namespace nttk

@@ -25,6 +25,7 @@
 #include <sys/prctl.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -110,6 +111,29 @@ hipError_t copy_many(const std::vector<CopyDesc>& v, hipStream_t s) {
   return hipSuccess;
 }
 
+// Per-request row-table entries of a launch whose kernels address the
+// requests' own buffers: limb-rows start .. start + rows - 1 of the launch are
+// rows 0 .. rows - 1 of a, b and out (row_bytes apart).
+constexpr uint32_t kMaxReqs = 64;  // requests per launch
+struct RowTabEntry {
+  uint64_t a, b, out;
+  uint32_t start, rows;
+};
+struct RowTabList {
+  RowTabEntry e[kMaxReqs];
+  uint64_t row_bytes;
+};
+
+__global__ void row_table_kernel(RowTabList l, uint64_t* ta, uint64_t* tb, uint64_t* to) {
+  const RowTabEntry q = l.e[blockIdx.y];
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < q.rows; j += gridDim.x * blockDim.x) {
+    const uint64_t off = (uint64_t)j * l.row_bytes;
+    ta[q.start + j] = q.a + off;
+    tb[q.start + j] = q.b + off;
+    to[q.start + j] = q.out + off;
+  }
+}
+
 struct Req {
   uint64_t id = 0;
   ntt_request r{};
@@ -168,7 +192,8 @@ struct ntt_server_s {
   std::vector<void*> arena;
   std::vector<size_t> arena_bytes;
   std::vector<hipEvent_t> free_events;  // completion events, reused (server thread only)
-  uint32_t max_reqs = 64;  // requests per launch
+  uint32_t max_reqs = kMaxReqs;
+  std::atomic<uint64_t> direct_launches{0};  // set by the server thread outside the lock
   std::map<std::tuple<uint32_t, uint32_t, std::vector<uint64_t>>, ntt_plan_t> plans;
 
   // Moduli already checked for (N, word_bits): a submit checks each modulus of
@@ -318,6 +343,54 @@ struct ntt_server_s {
           st = q->r.op == NTT_REQ_FORWARD ? ntt_forward(plan, q->r.out, q->r.batch, s)
                                            : ntt_inverse(plan, q->r.out, q->r.batch, s);
       }
+    } else if (pm && !host && polymul_rows_ok(run, run_batch)) {
+      // Two-pass polymul straight from and into the requests' buffers: the first
+      // column launch reads every a and b through row tables, the last one
+      // writes every out through one; nothing is gathered or scattered.
+      // Arena layout: O | workspace | limb constants (mixed launch) | tables.
+      uint64_t total = 0;
+      for (const Req* q : b->reqs) total += q->words * wb;
+      const uint64_t rows = (uint64_t)run_batch * run->L;
+      const size_t limb_off = ((size_t)2 * total + 255) & ~(size_t)255;
+      const size_t tab_off = (limb_off + (mixed ? (size_t)vp.L * sizeof(LimbDev) : 0) + 255) & ~(size_t)255;
+      const size_t need = tab_off + (size_t)3 * rows * sizeof(uint64_t);
+      if ((e = reserve(need)) != hipSuccess) return hip_fail(e, "server staging allocation");
+      unsigned char* base = static_cast<unsigned char*>(arena[b->stream]);
+      void* O = base;
+      void* WS = base + total;
+      uint64_t* ta = reinterpret_cast<uint64_t*>(base + tab_off);
+      uint64_t* tb = ta + rows;
+      uint64_t* to = tb + rows;
+      RowTabList list{};
+      list.row_bytes = (uint64_t)q0->r.N * wb;
+      uint32_t start = 0, most = 0;
+      for (size_t i = 0; i < b->reqs.size(); ++i) {
+        const Req* q = b->reqs[i];
+        const uint32_t qr = q->r.batch * (uint32_t)q->moduli.size();
+        list.e[i] = RowTabEntry{reinterpret_cast<uint64_t>(q->r.a), reinterpret_cast<uint64_t>(q->r.b),
+                                reinterpret_cast<uint64_t>(q->r.out), start, qr};
+        start += qr;
+        most = std::max(most, qr);
+      }
+      hipLaunchKernelGGL(row_table_kernel, dim3((most + 255) / 256, (uint32_t)b->reqs.size()), dim3(256),
+                         0, s, list, ta, tb, to);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "server row tables");
+      if (mixed) {
+        unsigned char* dl = base + limb_off;
+        vp.d_limbs = reinterpret_cast<LimbDev*>(dl);
+        std::vector<CopyDesc> lc;
+        for (size_t i = 0; i < b->reqs.size(); ++i) {
+          const Req* q = b->reqs[i];
+          const uint64_t unit = q->moduli.size() * sizeof(LimbDev) / 8;
+          lc.push_back(CopyDesc{reinterpret_cast<uint64_t*>(dl),
+                                reinterpret_cast<const uint64_t*>(src_plans[i]->d_limbs),
+                                unit * q->r.batch, unit});
+          dl += unit * 8 * q->r.batch;
+        }
+        if ((e = copy_many(lc, s)) != hipSuccess) return hip_fail(e, "server limb constants");
+      }
+      st = polymul_rows_into(run, to, ta, tb, run_batch, O, WS, s);
+      if (st == NTT_OK) direct_launches.fetch_add(1, std::memory_order_relaxed);
     } else {
       // Gather every operand into one contiguous batch, run one launch, scatter.
       // Arena layout: A | B | O | polymul workspace (polymul), A (transforms);
@@ -702,6 +775,7 @@ ntt_status ntt_server_counters_get(ntt_server_t s, ntt_server_counters* c) {
   if (!s || !c) return fail(NTT_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(s->mu);
   *c = s->ctr;
+  c->direct_launches = s->direct_launches.load(std::memory_order_relaxed);
   return NTT_OK;
 }
 

@@ -113,6 +113,10 @@ def test_serving_mix_at_full_size(flags):
     mixed, infos, c = _run(reqs, flags, streams=4, budget=64 << 30)
     alone, _, _ = _run(reqs, ntt.SERVER_SERIAL, streams=1, budget=64 << 30)
     assert max(x["batched_with"] for x in infos) > 1, "the mix should have batched something"
+    if flags & ntt.SERVER_MERGE_MODULI:
+        # batched 2^16 products run in place through row tables, without staging copies
+        assert any(x["batched_with"] > 1 for x, q in zip(infos, reqs) if q[1] == 1 << 16)
+        assert c["direct_launches"] >= 1
     for req, m, s in zip(reqs, mixed, alone):
         w = oracle.polymul(req[5], req[6], req[2])
         assert np.array_equal(m, w)
@@ -156,7 +160,46 @@ def test_requests_of_different_moduli_share_launches_word_for_word(memory):
     same, _, c_same = _run(reqs, 0, streams=1, memory=memory)
     assert c["merged_launches"] >= 1 and c_same["merged_launches"] == 0
     assert c["launches"] < c_same["launches"]
+    if memory == ntt.REQ_DEVICE:
+        assert c["direct_launches"] >= 1      # two-pass products at 2^12 and 2^14
+    else:
+        assert c["direct_launches"] == 0 and c_same["direct_launches"] == 0
     for req, m, s in zip(reqs, merged, same):
         w = _want(req)
         assert np.array_equal(m, w)
         assert np.array_equal(s, w)
+
+
+@pytest.mark.parametrize("flags", [0, ntt.SERVER_MERGE_MODULI])
+def test_batched_two_pass_products_read_and_write_the_requests_in_place(flags):
+    """Two-pass products (N = 2^16 and 2^14) batched from a burst run straight
+    from the requests' buffers through row tables: every result equals the
+    oracle's, including a request whose output buffer is its own first operand."""
+    p50 = synth.c2_primes(4)
+    reqs = []
+    for i in range(14):
+        N = 1 << 16 if i % 2 == 0 else 1 << 14
+        L = 3 if not flags else 1 + i % 4
+        pairs = 1 + (i % 3 == 0)
+        a = synth.uniform_poly(7000 + 2 * i, p50[:L], pairs, N)
+        b = synth.uniform_poly(7001 + 2 * i, p50[:L], pairs, N)
+        reqs.append((ntt.REQ_POLYMUL, N, p50[:L], 64, pairs, a, b))
+    got, infos, c = _run(reqs, flags, streams=1)
+    assert c["direct_launches"] >= 1
+    assert max(x["batched_with"] for x in infos) > 1
+    for req, g in zip(reqs, got):
+        assert np.array_equal(g, oracle.polymul(req[5], req[6], req[2]))
+    # out aliasing a: the operands are consumed by the first launch before the
+    # last one writes
+    da = [to_device(r[5], 64) for r in reqs]
+    db = [to_device(r[6], 64) for r in reqs]
+    torch.cuda.synchronize()
+    with ntt.Server(8 << 30, 1, 0, flags) as srv:
+        batch = [(op, N, mods, wb, pairs, x.data_ptr(), y.data_ptr(), x.data_ptr())
+                 for (op, N, mods, wb, pairs, _, _), x, y in zip(reqs, da, db)]
+        ids = srv.replay(batch, [0.0] * len(batch))
+        [srv.wait(i, 120000) for i in ids]
+        assert srv.counters()["direct_launches"] >= 1
+    torch.cuda.synchronize()
+    for req, x in zip(reqs, da):
+        assert np.array_equal(to_host(x, 64).astype(np.uint64), oracle.polymul(req[5], req[6], req[2]))
