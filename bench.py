@@ -271,7 +271,11 @@ def run_gpu(args):
     torch.cuda.synchronize()
     ms_other = t0.elapsed_time(t1) / args.steps
     # The same steps with the product's workspace from the library's fixed per-GPU
-    # scratch (ntt_polymul_noalloc) instead of the stream-ordered pool.
+    # scratch (ntt_polymul_noalloc) instead of the stream-ordered pool.  Its first
+    # call on a device looks up the scratch array's address (tens of ms, once per
+    # process): one untimed step first.
+    step(0, noalloc=True)
+    torch.cuda.synchronize()
     t0.record(stream)
     for i in range(args.steps):
         step(i, noalloc=True)

@@ -341,7 +341,9 @@ ntt_status ntt_polymul(ntt_plan_t plan, void* out, const void* a, const void* b,
  *     time on one GPU (several streams, unordered host threads) race on it and
  *     may return wrong words; order them on one stream.
  *   - the array's device address is looked up on the first call on each
- *     device (NTT_EDEVICE if that fails). */
+ *     device (NTT_EDEVICE if that fails); that first call takes tens of
+ *     milliseconds longer (the runtime loads the module's device globals), so
+ *     a caller with a latency budget makes one call at set-up. */
 ntt_status ntt_polymul_noalloc(ntt_plan_t plan, void* out, const void* a, const void* b,
                                uint32_t batch, void* stream);
 
