@@ -147,3 +147,35 @@ def test_basis_ext_create_rejects_bad_arguments_before_touching_the_device():
     assert lib.ntt_mod_up(None, None, None, 1, None) == 1
     assert lib.ntt_mod_down(None, None, None, 1, None) == 1
     assert lib.ntt_basis_ext_destroy(None) == 1
+
+
+def test_tuning_table_round_trips_on_the_host(tmp_path):
+    """The tuning table loads, merges and saves every kind it records (split,
+    ragged row length, row radices, column workgroup size) without a device, and
+    a file without entries is refused."""
+    import json
+    entries = [{"kind": 0, "log_n": 16, "cls": 1, "bucket": 7, "value": 4, "us": 107.5},
+               {"kind": 1, "log_n": 16, "cls": 0, "bucket": 0, "value": 12, "us": 900.0},
+               {"kind": 2, "log_n": 16, "cls": 1, "bucket": 7, "value": 3, "us": 0.0},
+               {"kind": 3, "log_n": 16, "cls": 1, "bucket": 7, "value": 4, "us": 0.0},
+               {"kind": 4, "log_n": 16, "cls": 1, "bucket": 7, "value": 4, "us": 0.0},
+               {"kind": 5, "log_n": 16, "cls": 1, "bucket": 7, "value": 128, "us": 107.1}]
+    src = tmp_path / "in.json"
+    src.write_text(json.dumps({"version": 1, "entries": entries}))
+    out = tmp_path / "out.json"
+    try:
+        ntt.tune_clear()
+        ntt.tune_load(str(src))
+        ntt.tune_save(str(out))
+        got = json.load(open(out))
+        assert got["arch"] == "gfx950"
+        key = lambda e: (e["kind"], e["log_n"], e["cls"], e["bucket"])
+        assert sorted((key(e), e["value"]) for e in got["entries"]) == \
+            sorted((key(e), e["value"]) for e in entries)
+        bad = tmp_path / "bad.json"
+        bad.write_text(json.dumps({"version": 1}))
+        with pytest.raises(ntt.NTTError) as ei:
+            ntt.tune_load(str(bad))
+        assert ei.value.name == "NTT_EINVAL"
+    finally:
+        ntt.tune_clear()
