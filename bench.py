@@ -291,7 +291,7 @@ def run_gpu(args):
     # 2 N W (every coefficient read and written once) + the twiddles, 16 N bytes
     # per modulus per launch shared by the 4 polynomials of that modulus: 1.25 MiB
     # at N = 2^16, W = 8 B; 144 limb transforms per call.
-    reps = 4 * args.sets
+    reps = 16 * args.sets
     fwd_mean = _time(torch, lambda: plan.forward(X[next(rot) % args.sets], stream), reps, stream)
     inv_mean = _time(torch, lambda: plan.inverse(X[next(rot) % args.sets], stream), reps, stream)
     fwd_ms = timed_calls(torch, lambda i: plan.forward(X[i % args.sets], stream), reps, stream)
@@ -721,7 +721,72 @@ def run_cpu_baseline(args):
             "sample": f"{steps} whole steps of the same workload (4x36x2^16, fwd+pointwise+inv+polymul), "
                       f"{el:.1f} s, {cores} threads over (poly, limb) rows",
             "one_core": {"value": 72 * reps1 / el1, "unit": "limb-NTT/s", "cores": 1,
-                         "sample": f"{reps1} x forward + inverse of one 36-limb 2^16 polynomial, {el1:.1f} s"}}
+                         "sample": f"{reps1} x forward + inverse of one 36-limb 2^16 polynomial, {el1:.1f} s"},
+            "per_config": run_cpu_per_config(args, cores)}
+
+
+def run_cpu_per_config(args, cores: int) -> dict:
+    """The oracle on the other configurations, each repeated for about an eighth
+    of cpu_seconds (at least once): C1 latency shape on one core, the C3 TFHE
+    batch (2048 forward, MAC 6 x 2, 684 inverse), the first 16 instances of the
+    C4 ragged mix (forward + inverse), and the C5 request mix (polymul per
+    request, in arrival order)."""
+    import oracle
+    from paper_2410_05934_amd import synth
+    budget = args.cpu_seconds / 8
+
+    def repeat(fn):
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            fn(n)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return n, el
+
+    out = {}
+    q1 = synth.c1_prime(0)
+    x1 = synth.uniform_poly(args.seed, [q1], 1, 1 << 10)
+    n, el = repeat(lambda i: oracle.inverse(oracle.forward(x1, [q1], 1), [q1], 1))
+    out["c1"] = {"value": round(n / el, 1), "unit": "forward+inverse pairs/s", "cores": 1,
+                 "sample": f"{n} x forward + inverse of one 2^10 polynomial, {el:.1f} s"}
+    q3 = synth.c3_prime()
+    x3 = synth.uniform_poly(args.seed, [q3], 2048, 1 << 10)
+    k3 = synth.uniform_poly(6, [q3], 12, 1 << 10).reshape(6, 2, 1, 1 << 10)
+
+    def c3(i):
+        acc = oracle.mac(oracle.forward(x3, [q3], cores), k3, [q3], 6, 2)
+        oracle.inverse(acc.reshape(-1, 1, 1 << 10), [q3], cores)
+
+    n, el = repeat(c3)
+    out["c3"] = {"value": round((2048 + 684) * n / el, 1), "unit": "limb-NTT/s", "cores": cores,
+                 "sample": f"{n} x (2048 forward, MAC, 684 inverse) at 2^10, {el:.1f} s"}
+    inst = synth.c4_instances(args.seed)[:16]
+    xs = [synth.uniform_poly(synth.derive_seed(args.seed, j), r.moduli, 1, r.N) for j, r in enumerate(inst)]
+    rows = sum(len(r.moduli) for r in inst)
+
+    def c4(i):
+        for r, x in zip(inst, xs):
+            oracle.inverse(oracle.forward(x, r.moduli, cores), r.moduli, cores)
+
+    n, el = repeat(c4)
+    out["c4"] = {"value": round(2 * rows * n / el, 1), "unit": "limb-NTT/s", "cores": cores,
+                 "sample": f"{n} x forward + inverse of the first 16 ragged instances ({rows} limb-rows), {el:.1f} s"}
+    reqs = synth.c5_requests(args.seed, 64, 1000.0)
+    ops = [(synth.uniform_poly(r.seed, r.moduli, r.pairs, r.N), synth.uniform_poly(r.seed + 1, r.moduli, r.pairs, r.N),
+            r.moduli) for r in reqs]
+    done = [0]
+
+    def c5(i):
+        a, b, m = ops[i % len(ops)]
+        oracle.polymul(a, b, m, cores)
+        done[0] += 1
+
+    n, el = repeat(c5)
+    out["c5"] = {"value": round(n / el, 1), "unit": "req/s", "cores": cores,
+                 "sample": f"{n} requests of the serving mix (polymul each, in arrival order), {el:.1f} s"}
+    return out
 
 
 _CLS = {"ArF64S": "f64s", "ArF64L": "f64l", "ArI64": "i64"}
