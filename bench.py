@@ -316,11 +316,19 @@ def run_gpu(args):
     if vi and all(v is not None for v in vi):
         valu = {"insts_per_launch": sum(vi), "issue_frac": round(valu_frac(sum(vi), t_avg_s), 4),
                 "peak": "1024 SIMDs x one wave64 VALU instruction per 4 cycles at 2.4 GHz"}
+    # The measured copy rate for the same coefficients: a device copy of one 75.5 MB
+    # set (cold, over the rotating sets) into one of two destination buffers.
+    dst = [torch.empty_like(X[0]) for _ in range(2)]
+    copy_mean = _time(torch, lambda: dst[next(rot) % 2].copy_(X[next(rot) % args.sets]), reps, stream)
+    copy_gbps = 2 * X[0].numel() * 8 / (copy_mean * 1e-3) / 1e9
+    del dst
     roofline = {"bound": "hbm", "kernel": "forward transform, 4 x 36 x 2^16: " + " + ".join(sorted(fwd_kernels)),
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": alg, "avg_launch_us": round(fwd_mean * 1e3, 2),
-                "time_percentiles_ms_event_per_call": t_fwd, "valu": valu, "per_kernel": fwd_kernels}
+                "time_percentiles_ms_event_per_call": t_fwd, "valu": valu,
+                "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
+                "per_kernel": fwd_kernels}
     _log(f"[bench] forward transform: {fwd_mean * 1e3:.2f} us, {achieved:.1f} GB/s = "
          f"{achieved / HBM_PEAK_GBS:.4f} of HBM peak; kernels {fwd_kernels}")
     extra = {"breakdown": breakdown, "ms_per_step_with_launch_events": round(ms_events, 4),
