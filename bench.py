@@ -730,7 +730,21 @@ def run_cpu_baseline(args):
                       f"{el:.1f} s, {cores} threads over (poly, limb) rows",
             "one_core": {"value": 72 * reps1 / el1, "unit": "limb-NTT/s", "cores": 1,
                          "sample": f"{reps1} x forward + inverse of one 36-limb 2^16 polynomial, {el1:.1f} s"},
-            "per_config": run_cpu_per_config(args, cores)}
+            "host": _host_cpu(), "per_config": run_cpu_per_config(args, cores)}
+
+
+def _host_cpu() -> dict:
+    """The host's CPU model (/proc/cpuinfo) and the threads the OS reports."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "os_cpu_count": os.cpu_count()}
 
 
 def run_cpu_per_config(args, cores: int) -> dict:
