@@ -475,12 +475,31 @@ def run_batched_vs_plain(args, torch, plan2, X, x2, ctr, stream, out):
     t_pc = _time(torch, cold_plain, 4 * args.sets, stream)
     t_b = _time(torch, lambda: plan2.forward(x2, stream), 20, stream)
     t_p = _time(torch, lambda: [plan2.forward(x2[i:i + 1], stream) for i in range(4)], 20, stream)
+    # One launch per (polynomial, limb): a one-modulus plan per limb, each call on one
+    # limb-row of the same buffers (144 calls per forward).
+    import paper_2410_05934_amd as ntt
+    from paper_2410_05934_amd import synth
+    limb_plans = [ntt.Plan(plan2.N, [q], 64) for q in synth.c2_primes(36)]
+
+    def per_limb(x):
+        for i in range(4):
+            for l, pl in enumerate(limb_plans):
+                pl.forward(x[i:i + 1, l:l + 1], stream)
+    t_lc = _time(torch, lambda: per_limb(X[next(ctr) % args.sets]), 2 * args.sets, stream)
+    t_l = _time(torch, lambda: per_limb(x2), 10, stream)
+    for pl in limb_plans:
+        pl.close()
     out["c2_forward"] = {"batched_us": round(t_bc * 1e3, 2), "per_poly_launch_us": round(t_pc * 1e3, 2),
+                         "per_limb_launch_us": round(t_lc * 1e3, 2),
                          "batched_limb_ntt_per_s": 144 / (t_bc * 1e-3),
                          "batched_over_plain": round(t_pc / t_bc, 3),
+                         "batched_over_per_limb": round(t_lc / t_bc, 3),
                          "warm_batched_us": round(t_b * 1e3, 2), "warm_per_poly_launch_us": round(t_p * 1e3, 2),
+                         "warm_per_limb_launch_us": round(t_l * 1e3, 2),
                          "warm_batched_over_plain": round(t_p / t_b, 3),
-                         "note": "cold: rotating sets; warm: one 75.5 MB set, Infinity-Cache resident"}
+                         "warm_batched_over_per_limb": round(t_l / t_b, 3),
+                         "note": "cold: rotating sets; warm: one 75.5 MB set, Infinity-Cache resident; plain: one "
+                                 "call per RNS polynomial (all its limbs); per limb: one call per (polynomial, limb)"}
 
 
 def run_c3(args, torch, ntt, synth, to_device, empty_device, stream, out):
