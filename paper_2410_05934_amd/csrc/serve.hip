@@ -227,11 +227,14 @@ struct ntt_server_s {
     *st = ntt_plan_create(&p, q->r.N, q->moduli.data(), (uint32_t)q->moduli.size(), q->r.word_bits, 0);
     if (*st != NTT_OK) return nullptr;
     plans[key] = p;
+    std::lock_guard<std::mutex> lk(mu);  // counters are read under the lock
     ctr.plans_cached = plans.size();
     return p;
   }
 
-  // Issue one batch (all requests share a shape).  Called with mu held.
+  // Issue one batch: requests of one shape, or (NTT_SERVER_MERGE_MODULI) of one
+  // merge key.  Called by the server thread without the lock; it takes the
+  // lock only to update the counters.
   ntt_status launch(Batch* b) {
     const double t = now_s();
     uint32_t polys = 0;
@@ -324,6 +327,7 @@ struct ntt_server_s {
       if (r == hipSuccess) arena_bytes[me] = grow;
       uint64_t held = 0;
       for (size_t j = 0; j < arena.size(); ++j) held += arena_bytes[j];
+      std::lock_guard<std::mutex> lk(mu);
       ctr.arena_bytes = held;
       ctr.max_arena_bytes = std::max(ctr.max_arena_bytes, held);
       return r;
