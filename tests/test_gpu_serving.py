@@ -170,20 +170,30 @@ def test_requests_of_different_moduli_share_launches_word_for_word(memory):
         assert np.array_equal(s, w)
 
 
+_CLASS_PRIMES = {
+    "f64": (64, lambda: synth.c2_primes(4)),                                  # fp64 class, < 2^50
+    "i64": (64, lambda: synth.primes_below(1 << 61, 1 << 17, 4)),             # 64-bit integer class
+    "u32": (32, lambda: synth.primes_below(1 << 32, 1 << 17, 4)),             # 32-bit words
+}
+
+
+@pytest.mark.parametrize("cls", ["f64", "i64", "u32"])
 @pytest.mark.parametrize("flags", [0, ntt.SERVER_MERGE_MODULI])
-def test_batched_two_pass_products_read_and_write_the_requests_in_place(flags):
+def test_batched_two_pass_products_read_and_write_the_requests_in_place(flags, cls):
     """Two-pass products (N = 2^16 and 2^14) batched from a burst run straight
-    from the requests' buffers through row tables: every result equals the
-    oracle's, including a request whose output buffer is its own first operand."""
-    p50 = synth.c2_primes(4)
+    from the requests' buffers through row tables, in every arithmetic class:
+    every result equals the oracle's, including a request whose output buffer is
+    its own first operand."""
+    wb, primes = _CLASS_PRIMES[cls]
+    pool = primes()
     reqs = []
     for i in range(14):
         N = 1 << 16 if i % 2 == 0 else 1 << 14
         L = 3 if not flags else 1 + i % 4
         pairs = 1 + (i % 3 == 0)
-        a = synth.uniform_poly(7000 + 2 * i, p50[:L], pairs, N)
-        b = synth.uniform_poly(7001 + 2 * i, p50[:L], pairs, N)
-        reqs.append((ntt.REQ_POLYMUL, N, p50[:L], 64, pairs, a, b))
+        a = synth.uniform_poly(7000 + 2 * i, pool[:L], pairs, N)
+        b = synth.uniform_poly(7001 + 2 * i, pool[:L], pairs, N)
+        reqs.append((ntt.REQ_POLYMUL, N, pool[:L], wb, pairs, a, b))
     got, infos, c = _run(reqs, flags, streams=1)
     assert c["direct_launches"] >= 1
     assert max(x["batched_with"] for x in infos) > 1
@@ -191,15 +201,15 @@ def test_batched_two_pass_products_read_and_write_the_requests_in_place(flags):
         assert np.array_equal(g, oracle.polymul(req[5], req[6], req[2]))
     # out aliasing a: the operands are consumed by the first launch before the
     # last one writes
-    da = [to_device(r[5], 64) for r in reqs]
-    db = [to_device(r[6], 64) for r in reqs]
+    da = [to_device(r[5], wb) for r in reqs]
+    db = [to_device(r[6], wb) for r in reqs]
     torch.cuda.synchronize()
     with ntt.Server(8 << 30, 1, 0, flags) as srv:
-        batch = [(op, N, mods, wb, pairs, x.data_ptr(), y.data_ptr(), x.data_ptr())
-                 for (op, N, mods, wb, pairs, _, _), x, y in zip(reqs, da, db)]
+        batch = [(op, N, mods, w, pairs, x.data_ptr(), y.data_ptr(), x.data_ptr())
+                 for (op, N, mods, w, pairs, _, _), x, y in zip(reqs, da, db)]
         ids = srv.replay(batch, [0.0] * len(batch))
         [srv.wait(i, 120000) for i in ids]
         assert srv.counters()["direct_launches"] >= 1
     torch.cuda.synchronize()
     for req, x in zip(reqs, da):
-        assert np.array_equal(to_host(x, 64).astype(np.uint64), oracle.polymul(req[5], req[6], req[2]))
+        assert np.array_equal(to_host(x, wb).astype(np.uint64), oracle.polymul(req[5], req[6], req[2]))
