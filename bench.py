@@ -621,6 +621,7 @@ def run_serving(args, out):
         "serial_capacity_req_per_s": res["serial"]["capacity_req_per_s"],
         "batched_over_serial_capacity": res["batched_over_serial_capacity"],
         "merged_over_batched_capacity": res["merged_over_batched_capacity"],
+        "small_budget": res["small_budget"],
         "batched": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["batched"]["open_loop"]],
         "serial": [{"fraction": o["fraction"], **{k: o[k] for k in keep}} for o in res["serial"]["open_loop"]],
     }

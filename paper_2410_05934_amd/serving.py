@@ -118,10 +118,11 @@ def run_load(server, work: Workload, rate: float | None, ntt_mod) -> dict:
 
 
 def sweep(n_requests: int, fractions, budget: int = 64 << 30, streams: int = 4, seed: int = 0,
-          serial_too: bool = True, merged_too: bool = True) -> dict:
+          serial_too: bool = True, merged_too: bool = True, small_budget: int = 1 << 30) -> dict:
     """Capacity (all requests at t = 0) and open-loop load at `fractions` of it,
     per server mode: "batched" (the default server), "merged" (also merging
-    moduli; capacity alone) and "serial"."""
+    moduli; capacity alone) and "serial"; then the default server's capacity
+    under `small_budget` bytes (0: skipped)."""
     import paper_2410_05934_amd as ntt
     reqs = synth.c5_requests(seed, n_requests, 1000.0)
     work = Workload(reqs, seed)
@@ -147,6 +148,17 @@ def sweep(n_requests: int, fractions, budget: int = 64 << 30, streams: int = 4, 
     if merged_too:
         out["merged_over_batched_capacity"] = (out["merged"]["capacity_req_per_s"]
                                                / out["batched"]["capacity_req_per_s"])
+    if small_budget:
+        # The same burst under a small HBM budget: admission holds requests back
+        # and the staging arenas stay inside the budget.
+        with ntt.Server(small_budget, streams, 0, 0) as srv:
+            run_load(srv, _subset(work, 256), None, ntt)
+            cap = run_load(srv, work, None, ntt)
+            c = srv.counters()
+        out["small_budget"] = {"budget_bytes": small_budget, "capacity_req_per_s": cap["achieved_req_per_s"],
+                               "p99_ms": cap["p99_ms"], "launches": cap["launches"],
+                               "max_inflight_bytes": c["max_inflight_bytes"],
+                               "max_arena_bytes": c["max_arena_bytes"], "rejected": c["rejected"]}
     return out
 
 
