@@ -483,8 +483,10 @@ typedef struct ntt_server_s* ntt_server_t;
 ntt_status ntt_server_create(ntt_server_t* out, uint64_t budget_bytes, uint32_t n_streams,
                              uint32_t max_batch, uint32_t flags);
 
-/* Queue a request; *id identifies it.  A request larger than the budget is
- * rejected here with NTT_ENOMEM, one of batch * L * N >= 2^32 words with
+/* Queue a request; *id identifies it.  A request holds, while in flight, its
+ * operand bytes times 4 (polymul: inputs, output, workspace) or 2 (transforms)
+ * plus 128 bytes per limb-row and 1 KiB (staged constants, row tables,
+ * alignment).  A request larger than the budget is rejected here with NTT_ENOMEM, one of batch * L * N >= 2^32 words with
  * NTT_EINVAL.  A launch gathers requests only while their words stay below
  * 2^32 (the library's per-call limit), so a request that succeeds alone also
  * succeeds in any mix; its result is the same word for word. */

@@ -713,9 +713,13 @@ ntt_status ntt_server_submit(ntt_server_t s, const ntt_request* r, uint64_t* id)
   }
   const uint64_t opnd = q->words * (r->word_bits / 8);
   // Device bytes while in flight: staging for inputs and output (+ the
-  // polymul workspace when the transform has a column pass).
+  // polymul workspace when the transform has a column pass), and per limb-row
+  // the constants a merged launch copies and the three row-table entries of an
+  // in-place launch, plus alignment slack: a launch's arena never needs more
+  // than the bytes its requests were admitted with.
   const uint64_t nbuf = r->op == NTT_REQ_POLYMUL ? 4 : 2;
-  q->bytes = opnd * nbuf;
+  const uint64_t limb_rows = (uint64_t)r->batch * r->num_moduli;
+  q->bytes = opnd * nbuf + limb_rows * (sizeof(LimbDev) + 3 * sizeof(uint64_t)) + 1024;
   std::lock_guard<std::mutex> lk(s->mu);
   q->id = s->next_id++;
   q->info.id = q->id;
